@@ -77,35 +77,37 @@ def max_threads() -> int:
 
 
 def ring_x(beta) -> np.ndarray:
-    """The ring definition x_j = cos(beta_j), evaluated in long double, rounded once."""
+    """Rings from colatitudes: x_j = cos(beta_j) evaluated in long double, rounded once."""
     beta = _c(beta, np.float64)
     x = np.empty_like(beta)
     _load().oracle_ring_x(beta.size, _ptr(beta), _ptr(x))
     return x
 
 
-def wigner_d(lmax: int, mb, msky, beta, nthreads: int = 0, split: bool = False):
-    """d^l_{mb[i],msky[i]}(beta[j]) for l in [0, lmax]; shape (npair, lmax+1, nring).
+def wigner_d(lmax: int, mb, msky, xring, nthreads: int = 0, split: bool = False):
+    """d^l_{mb[i],msky[i]}(beta_j) for l in [0, lmax]; shape (npair, lmax+1, nring).
+
+    Ring j is given by xring[j] = cos(beta_j) (use ring_x to turn colatitudes into rings).
 
     With split=True returns (mant, ex) with d = mant * 2^ex, mant in [0.5, 1),
     which represents values far outside the double range exactly."""
     mb = _c(np.atleast_1d(mb), np.int32)
     msky = _c(np.atleast_1d(msky), np.int32)
-    beta = _c(np.atleast_1d(beta), np.float64)
+    xr = _c(np.atleast_1d(xring), np.float64)
     if mb.shape != msky.shape:
         raise ValueError("mb and msky must have the same length")
-    shape = (mb.size, lmax + 1, beta.size)
+    shape = (mb.size, lmax + 1, xr.size)
     lib = _load()
     if split:
         mant = np.empty(shape, np.float64)
         ex = np.empty(shape, np.int64)
-        rc = lib.oracle_wigner_d(lmax, mb.size, _ptr(mb), _ptr(msky), beta.size, _ptr(beta),
+        rc = lib.oracle_wigner_d(lmax, mb.size, _ptr(mb), _ptr(msky), xr.size, _ptr(xr),
                                  None, _ptr(mant), _ptr(ex), nthreads)
         if rc:
             raise ValueError("oracle_wigner_d: invalid arguments (%d)" % rc)
         return mant, ex
     d = np.empty(shape, np.float64)
-    rc = lib.oracle_wigner_d(lmax, mb.size, _ptr(mb), _ptr(msky), beta.size, _ptr(beta),
+    rc = lib.oracle_wigner_d(lmax, mb.size, _ptr(mb), _ptr(msky), xr.size, _ptr(xr),
                              _ptr(d), None, None, nthreads)
     if rc:
         raise ValueError("oracle_wigner_d: invalid arguments (%d)" % rc)
@@ -119,60 +121,61 @@ def all_columns(lmax: int, mbmax: int):
     return mb, ms
 
 
-def totalconv_fwd(lmax: int, mbmax: int, beta, alm, blm, cols=None, rings=None,
+def totalconv_fwd(lmax: int, mbmax: int, xring, alm, blm, cols=None, rings=None,
                   eps: float = 0.0, nthreads: int = 0) -> np.ndarray:
     """C_{mb,msky}(beta_j) = sum_l conj(b_{l,mb}) d^l_{mb,msky}(beta_j) s_{l,msky}.
 
     cols: (mb array, msky array) or None for every (mb, msky >= 0) column.
     rings: ring indices or None for all.  Returns complex128 (ncol, nsel); with
-    cols=None and rings=None, shape (2*mbmax+1, lmax+1, nring)."""
-    beta = _c(beta, np.float64)
+    cols=None and rings=None, shape (2*mbmax+1, lmax+1, nring).  Rings are given by
+    xring[j] = cos(beta_j)."""
+    xr = _c(xring, np.float64)
     alm = _c(alm, np.complex128)
     blm = _c(blm, np.complex128)
     if alm.size != (lmax + 1) * (lmax + 2) // 2 or blm.shape != (2 * mbmax + 1, lmax + 1):
         raise ValueError("alm/blm shape mismatch")
     full = cols is None and rings is None
     cmb, cms = all_columns(lmax, mbmax) if cols is None else (_c(cols[0], np.int32), _c(cols[1], np.int32))
-    sel = np.arange(beta.size, dtype=np.int32) if rings is None else _c(rings, np.int32)
+    sel = np.arange(xr.size, dtype=np.int32) if rings is None else _c(rings, np.int32)
     out = np.empty((cmb.size, sel.size), np.complex128)
-    rc = _load().oracle_totalconv_fwd(lmax, mbmax, beta.size, _ptr(beta), _ptr(alm), _ptr(blm),
+    rc = _load().oracle_totalconv_fwd(lmax, mbmax, xr.size, _ptr(xr), _ptr(alm), _ptr(blm),
                                       cmb.size, _ptr(cmb), _ptr(cms), sel.size, _ptr(sel),
                                       float(eps), _ptr(out), nthreads)
     if rc:
         raise ValueError("oracle_totalconv_fwd: invalid arguments (%d)" % rc)
     if full:
-        return out.reshape(2 * mbmax + 1, lmax + 1, beta.size)
+        return out.reshape(2 * mbmax + 1, lmax + 1, xr.size)
     return out
 
 
-def column_sums(lmax: int, mbmax: int, beta, G, cols, nthreads: int = 0) -> np.ndarray:
+def column_sums(lmax: int, mbmax: int, xring, G, cols, nthreads: int = 0) -> np.ndarray:
     """u_l(col) = sum_j d^l_col(beta_j) G[col, j]; G has shape (ncol, nring).
     Returns complex long double as an array of shape (ncol, lmax+1, 2) (re, im)."""
-    beta = _c(beta, np.float64)
+    xr = _c(xring, np.float64)
     cmb, cms = _c(cols[0], np.int32), _c(cols[1], np.int32)
     G = _c(G, np.complex128)
-    if G.shape != (cmb.size, beta.size):
+    if G.shape != (cmb.size, xr.size):
         raise ValueError("G must have shape (ncol, nring)")
     u = np.empty((cmb.size, lmax + 1, 2), np.longdouble)
     if u.itemsize != ctypes.sizeof(ctypes.c_longdouble):
         raise RuntimeError("numpy longdouble does not match C long double")
-    rc = _load().oracle_totalconv_u(lmax, mbmax, beta.size, _ptr(beta), _ptr(G),
+    rc = _load().oracle_totalconv_u(lmax, mbmax, xr.size, _ptr(xr), _ptr(G),
                                     cmb.size, _ptr(cmb), _ptr(cms), _ptr(u), nthreads)
     if rc:
         raise ValueError("oracle_totalconv_u: invalid arguments (%d)" % rc)
     return u
 
 
-def totalconv_adj(lmax: int, mbmax: int, beta, alm, blm, Gbar, nthreads: int = 0):
+def totalconv_adj(lmax: int, mbmax: int, xring, alm, blm, Gbar, nthreads: int = 0):
     """Exact gradients (sky_bar, beam_bar) of the full forward for cotangent Gbar.
 
     Gbar has the layout of C, shape (2*mbmax+1, lmax+1, nring).  Returns complex128
     sky_bar (packed like alm) and beam_bar (shaped like blm)."""
-    beta = _c(beta, np.float64)
-    nring = beta.size
+    xr = _c(xring, np.float64)
+    nring = xr.size
     Gbar = _c(Gbar, np.complex128).reshape(2 * mbmax + 1, lmax + 1, nring)
     cmb, cms = all_columns(lmax, mbmax)
-    u = column_sums(lmax, mbmax, beta, Gbar.reshape(-1, nring), (cmb, cms), nthreads)
+    u = column_sums(lmax, mbmax, xr, Gbar.reshape(-1, nring), (cmb, cms), nthreads)
     u = u.reshape(2 * mbmax + 1, lmax + 1, lmax + 1, 2)     # [mb][msky][l][re/im]
     ure, uim = u[..., 0], u[..., 1]
     blm = _c(blm, np.complex128)

@@ -27,7 +27,8 @@
  *     with c = cos(beta/2), s = sin(beta/2), A = sqrt((2l)!/((l+m)!(l-m)!)).
  *   - F1 and F2 at l = 0 are set to 0 (the printed forms divide by zero; only
  *     the (0,0) chain reaches l = 0 and there d^{-1} = 0).
- *   - A ring is defined by x = cos(beta) rounded once to double; c and s are
+ *   - A ring is given by x = cos(beta) as a double (the per-ring cos(beta) the
+ *     paper precomputes, Sec. 4.2.2); c = cos(beta/2) and s = sin(beta/2) are
  *     derived from that x in long double.
  *   - A power that is zero contributes a factor 1 even when its base is zero;
  *     a zero base with a positive power makes the whole chain zero (Sec. 3.2,
@@ -50,9 +51,8 @@ typedef struct {
     int c_zero, s_zero;
 } ring_t;
 
-static void ring_setup(double beta, ring_t* r)
+static void ring_setup(double xd, ring_t* r)
 {
-    double xd = (double)cosl((ld)beta);   /* the ring's definition */
     ld x = (ld)xd;
     ld c = sqrtl((1.0L + x) / 2.0L);
     ld s = sqrtl((1.0L - x) / 2.0L);
@@ -197,10 +197,10 @@ static void set_threads(int nthreads)
     if (nthreads > 0) omp_set_num_threads(nthreads);
 }
 
-/* d[i][l][j] = d^l_{mb[i],ms[i]}(beta[j]) for l in [0,lmax] (zero for l < l0).
+/* d[i][l][j] = d^l_{mb[i],ms[i]}(beta_j), ring j given by xring[j] = cos(beta_j) for l in [0,lmax] (zero for l < l0).
  * If mant/ex are non-null they receive d = mant * 2^ex with mant in [0.5,1). */
 int oracle_wigner_d(int lmax, int npair, const int* mb, const int* ms,
-                    int nring, const double* beta,
+                    int nring, const double* xring,
                     double* d, double* mant, long long* ex, int nthreads)
 {
     if (check_pairs(lmax, npair, mb, ms) || nring < 0) return -1;
@@ -212,7 +212,10 @@ int oracle_wigner_d(int lmax, int npair, const int* mb, const int* ms,
         memset(ex, 0, sizeof(long long) * plane * npair);
     }
     ring_t* rings = (ring_t*)malloc(sizeof(ring_t) * (nring > 0 ? nring : 1));
-    for (int j = 0; j < nring; ++j) ring_setup(beta[j], &rings[j]);
+    for (int j = 0; j < nring; ++j) {
+        if (!(xring[j] >= -1.0 && xring[j] <= 1.0)) { free(rings); return -1; }
+        ring_setup(xring[j], &rings[j]);
+    }
     int err = 0;
 #pragma omp parallel
     {
@@ -286,10 +289,10 @@ static int check_conv(int lmax, int mbmax, int nring, int ncol, const int* cmb, 
     return 0;
 }
 
-/* C[i][k] = C_{cmb[i],cms[i]}(beta[ring_sel[k]])  (complex, interleaved).
+/* C[i][k] = C_{cmb[i],cms[i]}(beta_{ring_sel[k]})  (complex, interleaved); rings by x = cos(beta).
  * alm: packed m-major sky (m >= 0); blm: [2*mbmax+1][lmax+1] beam, row mb+mbmax.
  * cms[i] may be negative (the sky's reality relation supplies s_{l,-m}). */
-int oracle_totalconv_fwd(int lmax, int mbmax, int nring, const double* beta,
+int oracle_totalconv_fwd(int lmax, int mbmax, int nring, const double* xring,
                          const double* alm, const double* blm,
                          int ncol, const int* cmb, const int* cms,
                          int nsel, const int* ring_sel,
@@ -300,7 +303,10 @@ int oracle_totalconv_fwd(int lmax, int mbmax, int nring, const double* beta,
         if (ring_sel[k] < 0 || ring_sel[k] >= nring) return -1;
     set_threads(nthreads);
     ring_t* rings = (ring_t*)malloc(sizeof(ring_t) * nring);
-    for (int j = 0; j < nring; ++j) ring_setup(beta[j], &rings[j]);
+    for (int j = 0; j < nring; ++j) {
+        if (!(xring[j] >= -1.0 && xring[j] <= 1.0)) { free(rings); return -1; }
+        ring_setup(xring[j], &rings[j]);
+    }
     const int chunk = 64;
     int nchunk = (nsel + chunk - 1) / chunk;
     long long nitem = (long long)ncol * nchunk;
@@ -365,14 +371,17 @@ static void visit_u(int l, ld mant, long long ex, void* ctx)
  * u: [ncol][lmax+1] complex as pairs of long double.
  * The gradients then follow from u:  sky_bar_{l,msky} = sum_mb b_{l,mb} u_l(mb,msky),
  * beam_bar_{l,mb} = sum_msky s_{l,msky} conj(u_l(mb,msky)). */
-int oracle_totalconv_u(int lmax, int mbmax, int nring, const double* beta,
+int oracle_totalconv_u(int lmax, int mbmax, int nring, const double* xring,
                        const double* G, int ncol, const int* cmb, const int* cms,
                        ld* u, int nthreads)
 {
     if (check_conv(lmax, mbmax, nring, ncol, cmb, cms)) return -1;
     set_threads(nthreads);
     ring_t* rings = (ring_t*)malloc(sizeof(ring_t) * nring);
-    for (int j = 0; j < nring; ++j) ring_setup(beta[j], &rings[j]);
+    for (int j = 0; j < nring; ++j) {
+        if (!(xring[j] >= -1.0 && xring[j] <= 1.0)) { free(rings); return -1; }
+        ring_setup(xring[j], &rings[j]);
+    }
     memset(u, 0, sizeof(ld) * 2 * (long long)ncol * (lmax + 1));
     int err = 0;
 #pragma omp parallel
@@ -404,7 +413,7 @@ int oracle_totalconv_u(int lmax, int mbmax, int nring, const double* beta,
     return err;
 }
 
-/* x_j as the oracle defines the ring, for the tests. */
+/* cos(beta) evaluated in long double and rounded once: turns a colatitude into a ring. */
 int oracle_ring_x(int nring, const double* beta, double* x)
 {
     for (int j = 0; j < nring; ++j) x[j] = (double)cosl((ld)beta[j]);

@@ -6,8 +6,12 @@ path and the CPU oracle may be fed from it.
 
 Layouts (all complex arrays are complex128, i.e. interleaved FP64 pairs):
 
-* rings: ``beta[j] = pi * (j + 1/2) / nring`` for ``j = 0 .. nring-1``: an open,
-  equispaced grid in (0, pi) that is symmetric under beta -> pi - beta.
+* rings: colatitudes ``beta[j] = pi * (j + 1/2) / nring`` for ``j = 0 .. nring-1``, an
+  open equispaced grid in (0, pi).  A ring is handed to the library as
+  ``x[j] = cos(beta[j])`` (a double): ``ring_cosines`` evaluates the cosine in long
+  double, rounds it once, and makes the set exactly mirror-symmetric,
+  ``x[nring-1-j] = -x[j]`` (and ``x = 0`` on the equator ring when nring is odd),
+  so that ring pairs (beta, pi - beta) are exact pairs.
 * sky ``alm``: the coefficients s_{l,m} for 0 <= m <= l <= lmax, packed m-major
   (index ``m*(2*lmax+1-m)//2 + l``).  s_{l,-m} = (-1)^m conj(s_{l,m}) is implied
   (a real sky, Sec. 4.2.3 of the paper), so a_{l,0} is real.
@@ -44,6 +48,20 @@ def ring_colatitudes(nring: int) -> np.ndarray:
         raise ValueError("nring must be >= 1")
     j = np.arange(nring, dtype=np.float64)
     return np.pi * (j + 0.5) / nring
+
+
+def ring_cosines(nring: int) -> np.ndarray:
+    """x_j = cos(beta_j) on the equispaced grid, exactly mirror-symmetric."""
+    if nring < 1:
+        raise ValueError("nring must be >= 1")
+    pi = np.arccos(np.longdouble(-1.0))
+    j = np.arange(nring, dtype=np.longdouble)
+    x = np.cos(pi * (j + np.longdouble(0.5)) / np.longdouble(nring)).astype(np.float64)
+    h = nring // 2
+    x[nring - 1 - np.arange(h)] = -x[:h]
+    if nring % 2:
+        x[h] = 0.0
+    return x
 
 
 def alm_index(lmax: int, l, m):
@@ -138,8 +156,8 @@ class Detector:
     fwhm_arcmin: float
     ellipticity: float
 
-    def beta(self) -> np.ndarray:
-        return ring_colatitudes(self.nring)
+    def xring(self) -> np.ndarray:
+        return ring_cosines(self.nring)
 
     def blm(self) -> np.ndarray:
         return beam_blm(self.lmax, self.mbmax, self.fwhm_arcmin, self.ellipticity)
@@ -158,8 +176,8 @@ class Workload:
     sky_taper: float | None = None
     detectors: list = field(default_factory=list)
 
-    def beta(self) -> np.ndarray:
-        return ring_colatitudes(self.nring)
+    def xring(self) -> np.ndarray:
+        return ring_cosines(self.nring)
 
     def alm(self) -> np.ndarray:
         return sky_alm(self.lmax, self.sky_seed, self.sky_taper)

@@ -16,7 +16,8 @@ from paper_1002_1050_amd import synthetic as S
 
 
 def rings(n):
-    return np.pi * (np.arange(n) + 0.5) / n
+    """Ring cosines of the equispaced grid, exactly mirror-symmetric."""
+    return S.ring_cosines(n)
 
 
 def sky_get(alm, lmax):
@@ -44,13 +45,13 @@ def test_brute_force_tiny(orc):
     mp.mp.dps = 40
     from oracle import mpref
     L, M, n = 9, 3, 7
-    beta = rings(n)
-    x = orc.ring_x(beta)
+    xr = rings(n)
+    x = xr
     alm = random_sky(L, 3)
     blm = S.random_beam(L, M, 4)
     mbs = np.repeat(np.arange(-M, M + 1), 2 * L + 1).astype(np.int32)
     mss = np.tile(np.arange(-L, L + 1), 2 * M + 1).astype(np.int32)
-    C = orc.totalconv_fwd(L, M, beta, alm, blm, cols=(mbs, mss))
+    C = orc.totalconv_fwd(L, M, xr, alm, blm, cols=(mbs, mss))
     sg, bg = sky_get(alm, L), beam_get(blm, M)
     worst = 0.0
     for i in range(mbs.size):
@@ -64,17 +65,17 @@ def test_full_layout_and_delta_inputs(orc):
     """A unit sky at (l*, m*) and a unit beam at (l*, mb*) give C = d^{l*}_{mb*, m*} in that
     single column and zero elsewhere; checks layout, conjugation and the l-range."""
     L, M, n = 20, 4, 9
-    beta = rings(n)
+    xr = rings(n)
     for (ls, ms, mbs) in [(7, 3, -2), (20, 0, 4), (4, 4, 4), (13, 12, -3)]:
         alm = S.delta_sky(L, ls, ms, 1.0)
         blm = S.delta_beam(L, M, ls, mbs, 1.0)
-        C = orc.totalconv_fwd(L, M, beta, alm, blm)
-        d = orc.wigner_d(L, [mbs], [ms], beta)[0, ls]
+        C = orc.totalconv_fwd(L, M, xr, alm, blm)
+        d = orc.wigner_d(L, [mbs], [ms], xr)[0, ls]
         expect = np.zeros_like(C)
         expect[mbs + M, ms] = d
         np.testing.assert_allclose(C, expect, atol=1e-16, rtol=0)
         # complex weights: conj on the beam, none on the sky
-        C2 = orc.totalconv_fwd(L, M, beta, S.delta_sky(L, ls, ms, 2 - 1j), S.delta_beam(L, M, ls, mbs, 1j))
+        C2 = orc.totalconv_fwd(L, M, xr, S.delta_sky(L, ls, ms, 2 - 1j), S.delta_beam(L, M, ls, mbs, 1j))
         np.testing.assert_allclose(C2[mbs + M, ms], np.conj(1j) * (2 - 1j) * d, atol=1e-15)
 
 
@@ -83,12 +84,12 @@ def test_spherical_harmonic_special_case(orc):
     sqrt(4 pi/(2l+1)) Y_lm(theta, 0)  (Sec. 4 relation between Y_lm and D^l_{0m})."""
     mp.mp.dps = 30
     L, M, n = 24, 2, 5
-    beta = rings(n)
-    x = orc.ring_x(beta)
+    xr = rings(n)
+    x = xr
     th = [mp.acos(mp.mpf(v)) for v in x]
     alm = S.sky_alm(L, 11)
     blm = S.beam_blm(L, M, 300.0, 0.0)           # e = 0: only mb = 0 is non-zero
-    C = orc.totalconv_fwd(L, M, beta, alm, blm)
+    C = orc.totalconv_fwd(L, M, xr, alm, blm)
     for m in (0, 1, 5, 17):
         for j in range(n):
             ref = mp.mpc(0)
@@ -102,13 +103,13 @@ def test_spherical_harmonic_special_case(orc):
 def test_conjugate_symmetry(orc):
     """C_{-mb,-msky} = conj(C_{mb,msky}) for a real sky and a real-space beam (Sec. 4.2.3)."""
     L, M, n = 40, 6, 13
-    beta = rings(n)
+    xr = rings(n)
     alm = S.sky_alm(L, 5)
     blm = S.beam_blm(L, M, 200.0, 0.25)
     mbs = np.repeat(np.arange(-M, M + 1), L + 1).astype(np.int32)
     mss = np.tile(np.arange(0, L + 1), 2 * M + 1).astype(np.int32)
-    C = orc.totalconv_fwd(L, M, beta, alm, blm, cols=(mbs, mss))
-    Cn = orc.totalconv_fwd(L, M, beta, alm, blm, cols=(-mbs, -mss))
+    C = orc.totalconv_fwd(L, M, xr, alm, blm, cols=(mbs, mss))
+    Cn = orc.totalconv_fwd(L, M, xr, alm, blm, cols=(-mbs, -mss))
     np.testing.assert_allclose(Cn, np.conj(C), atol=1e-15, rtol=0)
 
 
@@ -116,27 +117,27 @@ def test_pi_minus_beta_pairing(orc):
     """C_{-mb,msky}(pi - beta) = sum_l conj(b_{l,-mb}) (-1)^{l-msky} d^l_{mb,msky}(beta) s_{l,msky}
     (appendix eq. pithetasym inside eq. convdef)."""
     L, M, n = 30, 4, 10
-    beta = rings(n)
+    xr = rings(n)
     alm = random_sky(L, 8)
     blm = S.random_beam(L, M, 9)
-    C = orc.totalconv_fwd(L, M, beta, alm, blm)
+    C = orc.totalconv_fwd(L, M, xr, alm, blm)
     sg = sky_get(alm, L)
     lsign = (-1.0) ** np.arange(L + 1)
     for mb in range(-M, M + 1):
         for ms in (0, 3, 11, 30):
-            d = orc.wigner_d(L, [mb], [ms], beta)[0]          # (L+1, n)
+            d = orc.wigner_d(L, [mb], [ms], xr)[0]          # (L+1, n)
             w = np.array([np.conj(blm[-mb + M, l]) * sg(l, ms) for l in range(L + 1)])
             pair = ((w * lsign * (-1.0) ** ms)[:, None] * d).sum(axis=0)
-            np.testing.assert_allclose(C[-mb + M, ms, ::-1], pair, atol=2e-13, rtol=0)
+            np.testing.assert_allclose(C[-mb + M, ms, ::-1], pair, atol=2e-15, rtol=0)
 
 
 def test_linearity(orc):
     L, M, n = 25, 3, 6
-    beta = rings(n)
+    xr = rings(n)
     a1, a2 = random_sky(L, 1), random_sky(L, 2)
     b1, b2 = S.random_beam(L, M, 1), S.random_beam(L, M, 2)
     lam = 0.7 - 1.3j
-    f = lambda a, b: orc.totalconv_fwd(L, M, beta, a, b)
+    f = lambda a, b: orc.totalconv_fwd(L, M, xr, a, b)
     np.testing.assert_allclose(f(a1 + lam * a2, b1), f(a1, b1) + lam * f(a2, b1), atol=1e-14)
     np.testing.assert_allclose(f(a1, b1 + lam * b2), f(a1, b1) + np.conj(lam) * f(a1, b2), atol=1e-14)
 
@@ -144,12 +145,12 @@ def test_linearity(orc):
 def test_ring_and_column_selection(orc):
     """Sampled columns and rings equal the corresponding slice of the full result."""
     L, M, n = 33, 5, 17
-    beta = rings(n)
+    xr = rings(n)
     alm, blm = S.sky_alm(L, 2), S.beam_blm(L, M, 100.0, 0.2)
-    full = orc.totalconv_fwd(L, M, beta, alm, blm)
+    full = orc.totalconv_fwd(L, M, xr, alm, blm)
     cols = (np.array([-5, 0, 3, 5], np.int32), np.array([33, 0, 7, 2], np.int32))
     sel = np.array([16, 0, 5], np.int32)
-    part = orc.totalconv_fwd(L, M, beta, alm, blm, cols=cols, rings=sel)
+    part = orc.totalconv_fwd(L, M, xr, alm, blm, cols=cols, rings=sel)
     for i in range(4):
         np.testing.assert_array_equal(part[i], full[cols[0][i] + M, cols[1][i], sel])
 
@@ -158,15 +159,15 @@ def test_eps_skip_bound(orc):
     """The paper's accumulation skip (Sec. 4.2.1): neglecting d below eps before its first
     crossing changes C by at most eps * sum_l |w_l|."""
     L, M, n = 200, 4, 64
-    beta = rings(n)
+    xr = rings(n)
     alm, blm = S.sky_alm(L, 4), S.beam_blm(L, M, 60.0, 0.2)
-    full = orc.totalconv_fwd(L, M, beta, alm, blm)
+    full = orc.totalconv_fwd(L, M, xr, alm, blm)
     eps = 1e-30
-    skip = orc.totalconv_fwd(L, M, beta, alm, blm, eps=eps)
+    skip = orc.totalconv_fwd(L, M, xr, alm, blm, eps=eps)
     bound = eps * np.abs(blm).sum(axis=1).max() * np.abs(alm).max() * (L + 1)
     assert np.max(np.abs(skip - full)) <= bound
     eps = 1e-3
-    skip = orc.totalconv_fwd(L, M, beta, alm, blm, eps=eps)
+    skip = orc.totalconv_fwd(L, M, xr, alm, blm, eps=eps)
     assert np.max(np.abs(skip - full)) > 0     # the switch does something
 
 
@@ -179,12 +180,12 @@ def _inner(u, v):
 def test_adjoint_dot_product(orc):
     """Re<C(s), G> = Re<s, sky_bar(G)> and Re<C(b), G> = Re<b, beam_bar(G)>."""
     L, M, n = 28, 4, 11
-    beta = rings(n)
+    xr = rings(n)
     alm = random_sky(L, 21)
     blm = S.random_beam(L, M, 22)
     G = S.random_cbar(L, M, n, 23)
-    C = orc.totalconv_fwd(L, M, beta, alm, blm)
-    sky_bar, beam_bar = orc.totalconv_adj(L, M, beta, alm, blm, G)
+    C = orc.totalconv_fwd(L, M, xr, alm, blm)
+    sky_bar, beam_bar = orc.totalconv_adj(L, M, xr, alm, blm, G)
     lhs = _inner(G, C)
     assert abs(lhs - _inner(sky_bar, alm)) <= 1e-13 * abs(lhs)
     assert abs(lhs.real - _inner(blm, beam_bar).real) <= 1e-13 * abs(lhs)
@@ -196,13 +197,13 @@ def test_adjoint_central_differences(orc):
     """L = 0.5 ||C - T||^2 is quadratic in each coefficient, so central differences equal the
     gradient up to rounding (PyTorch convention: grad = dL/dRe + i dL/dIm)."""
     L, M, n = 16, 2, 9
-    beta = rings(n)
+    xr = rings(n)
     alm = random_sky(L, 31)
     blm = S.random_beam(L, M, 32)
-    T = orc.totalconv_fwd(L, M, beta, random_sky(L, 33), blm)
-    loss = lambda a, b: 0.5 * np.sum(np.abs(orc.totalconv_fwd(L, M, beta, a, b) - T) ** 2)
-    G = orc.totalconv_fwd(L, M, beta, alm, blm) - T
-    sky_bar, beam_bar = orc.totalconv_adj(L, M, beta, alm, blm, G)
+    T = orc.totalconv_fwd(L, M, xr, random_sky(L, 33), blm)
+    loss = lambda a, b: 0.5 * np.sum(np.abs(orc.totalconv_fwd(L, M, xr, a, b) - T) ** 2)
+    G = orc.totalconv_fwd(L, M, xr, alm, blm) - T
+    sky_bar, beam_bar = orc.totalconv_adj(L, M, xr, alm, blm, G)
     rng = np.random.Generator(np.random.PCG64(7))
     h = 1e-3
     gmax = max(np.abs(sky_bar).max(), np.abs(beam_bar).max())
@@ -230,12 +231,12 @@ def test_adjoint_brute_force_tiny(orc):
     mp.mp.dps = 30
     from oracle import mpref
     L, M, n = 6, 2, 4
-    beta = rings(n)
-    x = orc.ring_x(beta)
+    xr = rings(n)
+    x = xr
     alm = random_sky(L, 41)
     blm = S.random_beam(L, M, 42)
     G = S.random_cbar(L, M, n, 43)
-    sky_bar, beam_bar = orc.totalconv_adj(L, M, beta, alm, blm, G)
+    sky_bar, beam_bar = orc.totalconv_adj(L, M, xr, alm, blm, G)
     sg = sky_get(alm, L)
     dd = {}
     for mb in range(-M, M + 1):
@@ -256,9 +257,9 @@ def test_adjoint_brute_force_tiny(orc):
 
 
 def test_invalid_conv_arguments(orc):
-    beta = rings(3)
+    xr = rings(3)
     with pytest.raises(ValueError):
-        orc.totalconv_fwd(4, 5, beta, S.sky_alm(4, 1), np.zeros((11, 5), complex))
+        orc.totalconv_fwd(4, 5, xr, S.sky_alm(4, 1), np.zeros((11, 5), complex))
     with pytest.raises(ValueError):
-        orc.totalconv_fwd(4, 1, beta, S.sky_alm(4, 1), np.zeros((3, 5), complex),
+        orc.totalconv_fwd(4, 1, xr, S.sky_alm(4, 1), np.zeros((3, 5), complex),
                           cols=(np.array([2], np.int32), np.array([0], np.int32)))

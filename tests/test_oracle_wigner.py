@@ -38,7 +38,7 @@ def test_explicit_sum_small_l(orc):
     x = orc.ring_x(beta)
     mb = [p[0] for p in PAIRS]
     ms = [p[1] for p in PAIRS]
-    d = orc.wigner_d(40, mb, ms, beta)
+    d = orc.wigner_d(40, mb, ms, x)
     worst = 0.0
     for i, (a, b) in enumerate(PAIRS):
         for j in range(beta.size):
@@ -55,7 +55,7 @@ def test_explicit_sum_many_columns(orc):
     beta = np.array([0.11, 1.3, 2.7])
     x = orc.ring_x(beta)
     pairs = [(a, b) for a in range(-12, 13, 3) for b in range(-12, 13, 2)]
-    d = orc.wigner_d(24, [p[0] for p in pairs], [p[1] for p in pairs], beta)
+    d = orc.wigner_d(24, [p[0] for p in pairs], [p[1] for p in pairs], x)
     worst = 0.0
     for i, (a, b) in enumerate(pairs):
         for j in range(3):
@@ -65,7 +65,7 @@ def test_explicit_sum_many_columns(orc):
 
 
 def test_zero_below_l0(orc):
-    d = orc.wigner_d(30, [3, -7, 0], [10, 2, -5], rings(7))
+    d = orc.wigner_d(30, [3, -7, 0], [10, 2, -5], orc.ring_x(rings(7)))
     assert np.all(d[0, :10] == 0) and np.all(d[1, :7] == 0) and np.all(d[2, :5] == 0)
     assert np.all(d[0, 10] != 0)
 
@@ -78,7 +78,7 @@ def test_diagonal_seed_closed_form(orc):
     x = orc.ring_x(beta).astype(np.longdouble)
     c2 = (1 + x) / 2
     for l in (0, 1, 5, 60, 700):
-        d = orc.wigner_d(l, [l], [l], beta)[0, l]
+        d = orc.wigner_d(l, [l], [l], orc.ring_x(beta))[0, l]
         ref = (c2 ** l).astype(np.float64)
         np.testing.assert_allclose(d, ref, rtol=2.3e-16, atol=0)   # one ulp: both round to double
 
@@ -86,7 +86,7 @@ def test_diagonal_seed_closed_form(orc):
 def test_identity_at_beta_zero(orc):
     """d^l_{m m'}(0) = delta_{m m'} (Sec. 4.2.1); exercises the zero-base rule."""
     pairs = [(a, b) for a in range(-6, 7) for b in range(-6, 7)]
-    d = orc.wigner_d(50, [p[0] for p in pairs], [p[1] for p in pairs], np.array([0.0]))
+    d = orc.wigner_d(50, [p[0] for p in pairs], [p[1] for p in pairs], np.array([1.0]))
     for i, (a, b) in enumerate(pairs):
         l0 = max(abs(a), abs(b))
         expect = 1.0 if a == b else 0.0
@@ -101,7 +101,7 @@ def test_legendre_special_cases(orc):
     beta = np.array([0.004, 0.9, 1.6, 3.1])
     x = orc.ring_x(beta)
     L = 1500
-    d = orc.wigner_d(L, [0, 5, 12], [0, 0, 0], beta)
+    d = orc.wigner_d(L, [0, 5, 12], [0, 0, 0], x)
     for j in range(beta.size):
         for l in (0, 1, 2, 77, 1499, 1500):
             assert abs(d[0, l, j] - float(mp.legendre(l, mp.mpf(x[j])))) <= 2e-15
@@ -118,7 +118,7 @@ def test_spherical_harmonic_relation(orc):
     x = orc.ring_x(theta)
     th = [mp.acos(mp.mpf(v)) for v in x]      # the ring's exact colatitude
     ms = [0, 1, 4, 9]
-    d = orc.wigner_d(30, [0] * len(ms), ms, theta)
+    d = orc.wigner_d(30, [0] * len(ms), ms, x)
     for i, m in enumerate(ms):
         for l in range(m, 31, 4):
             for j in range(3):
@@ -131,7 +131,7 @@ def test_spherical_harmonic_relation(orc):
 
 def test_appendix_symmetries(orc):
     """d_{m m'} = (-1)^{m-m'} d_{-m,-m'} = (-1)^{m-m'} d_{m' m} = d_{-m',-m}  (appendix)."""
-    beta = rings(11)
+    beta = orc.ring_x(rings(11))
     L = 120
     base = [(3, 1), (-4, 9), (10, -2), (0, 7), (-5, -5), (6, 6), (13, -13)]
     mb, ms = [], []
@@ -150,7 +150,8 @@ def test_appendix_symmetries(orc):
 def test_pi_minus_beta(orc):
     """d^l_{m m'}(pi - beta) = (-1)^{l-m'} d^l_{-m,m'}(beta)  (appendix, eq. pithetasym)."""
     n = 40
-    beta = rings(n)
+    from paper_1002_1050_amd import synthetic as S
+    beta = S.ring_cosines(n)                       # exactly mirror-symmetric: x[n-1-j] = -x[j]
     L = 60
     cols = [(2, 5), (-3, 1), (7, 7), (0, 0), (4, 0)]
     mb = [c[0] for c in cols] + [-c[0] for c in cols]
@@ -161,8 +162,7 @@ def test_pi_minus_beta(orc):
         lhs = d[k][:, ::-1]                         # ring n-1-j is pi - beta_j
         rhs = ((-1.0) ** (l - b)) * d[len(cols) + k]
         rhs[: max(abs(a), abs(b))] = 0
-        # the two rings differ by the rounding of their x: a few ulp times l^2
-        assert np.max(np.abs(lhs - rhs)) <= 1e-12
+        assert np.max(np.abs(lhs - rhs)) <= 1e-15
 
 
 def test_row_orthonormality(orc):
@@ -173,7 +173,7 @@ def test_row_orthonormality(orc):
         mp_ = np.arange(-l, l + 1)
         mb = np.repeat(mrows, mp_.size)
         ms = np.tile(mp_, len(mrows))
-        d = orc.wigner_d(l, mb, ms, beta)[:, l, :].reshape(len(mrows), mp_.size, beta.size)
+        d = orc.wigner_d(l, mb, ms, orc.ring_x(beta))[:, l, :].reshape(len(mrows), mp_.size, beta.size)
         for j in range(beta.size):
             g = d[:, :, j] @ d[:, :, j].T
             np.testing.assert_allclose(g, np.eye(len(mrows)), atol=5e-15)
@@ -197,7 +197,7 @@ def test_jacobi_form_large_l(orc):
         nring = pts[0]["nring"]
         beta = np.pi * (np.array(rr, dtype=np.float64) + 0.5) / nring
         x = orc.ring_x(beta)
-        mant, ex = orc.wigner_d(L, [mb], [ms], beta, split=True)
+        mant, ex = orc.wigner_d(L, [mb], [ms], x, split=True)
         for p in pts:
             j = rr.index(p["ring"])
             assert float.fromhex(p["x"]) == x[j]
@@ -223,7 +223,7 @@ def _first_peak_after(vals, start):
 def test_fig1_l_transition(orc):
     """Sec. 2 / Fig. 1 top: d^l_{0,10}(0.0996687) turns classical at l = 100 and its tallest
     peak is the first one after the transition; below l = 100 it is exponentially small."""
-    d = np.abs(orc.wigner_d(500, [0], [10], np.array([0.0996687]))[0, :, 0])
+    d = np.abs(orc.wigner_d(500, [0], [10], orc.ring_x([0.0996687]))[0, :, 0])
     lt = 0.5 * (math.sqrt(1 + 4 * 10 ** 2 / math.sin(0.0996687) ** 2) - 1)   # eq. classiccond
     assert abs(lt - 100) < 0.5
     arg = int(np.argmax(d[10:])) + 10
@@ -238,7 +238,7 @@ def test_fig1_m_transition(orc):
     text's l = 1000); the tallest peak is the last one before m' = 500, and |d| decays
     quickly above it."""
     ms = np.arange(0, 1001)
-    d = np.abs(orc.wigner_d(1000, np.zeros_like(ms), ms, np.array([0.52331]))[:, 1000, 0])
+    d = np.abs(orc.wigner_d(1000, np.zeros_like(ms), ms, orc.ring_x([0.52331]))[:, 1000, 0])
     mt = math.sin(0.52331) * math.sqrt(1000 * 1001)       # eq. classiccondm0
     assert abs(mt - 500) < 0.5
     arg = int(np.argmax(d))
@@ -252,7 +252,7 @@ def test_fig1_beta_transition(orc):
     """Sec. 2 / Fig. 1 bottom: d^{100}_{0,71}(beta) turns classical at beta = pi/4; the tallest
     peak on (0, pi/2] is the first one after it."""
     beta = np.linspace(math.pi / 2 / 2000, math.pi / 2, 2000)
-    d = np.abs(orc.wigner_d(100, [0], [71], beta)[0, 100, :])
+    d = np.abs(orc.wigner_d(100, [0], [71], orc.ring_x(beta))[0, 100, :])
     bt = math.asin(71 / math.sqrt(100 * 101))
     assert abs(bt - math.pi / 4) < 2e-3
     arg = int(np.argmax(d))
@@ -267,5 +267,7 @@ def test_fig1_beta_transition(orc):
 def test_invalid_arguments(orc):
     with pytest.raises(ValueError):
         orc.wigner_d(5, [6], [0], np.array([0.1]))
+    with pytest.raises(ValueError):
+        orc.wigner_d(5, [0], [0], np.array([1.5]))     # |x| > 1 is not a ring
     with pytest.raises(ValueError):
         orc.wigner_d(5, [0], [-6], np.array([0.1]))
