@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the total convolution on one MI355X: forward + adjoint.
+
+One step = totalconv_fwd (C from sky and beam) + totalconv_adj (sky and beam
+gradients from a fixed cotangent), both through the C ABI on torch's current
+stream, on the lmax 4096 / mbmax 14 / 8192-ring workload (synthetic seeded sky
+and beam, inputs resident in HBM before timing).  `value` counts the
+(l, mb, msky, beta) terms of both passes per second.
+
+Prints one JSON line.  Also reports, for the dominant kernel, its algorithmic
+FP64 rate against the vector-FP64 peak (HIP events around each launch on the
+stream it runs on), and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GHz
+# Algorithmic FP64 flops per (l, mb, msky, beta) term with the mirror-ring pairing:
+# one recursion step (5 flops: sub, 3 mul, fma as written in the paper) serves two
+# terms, and each term adds a complex weight times a real d (4 flops).
+FLOPS_PER_TERM_PAIRED = 6.5
+FLOPS_PER_TERM_UNPAIRED = 9.0
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="lmax4096")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="wall-clock budget of the oracle sample (0 disables)")
+    p.add_argument("--fwd-only", action="store_true", help="time the forward alone")
+    return p.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, x, alm, blm, G_cols_fn, seconds):
+    """Oracle forward + adjoint column sums on a seeded sample of whole columns."""
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(2024))
+    nb = 2 * w.mbmax + 1
+    order = rng.permutation(nb * (w.lmax + 1))
+    done_terms = 0
+    ncols = 0
+    elapsed = 0.0          # oracle time only (the cotangent copies are excluded)
+    batch = 16
+    for i in range(0, order.size, batch):
+        sel = order[i:i + batch]
+        mb = (sel // (w.lmax + 1) - w.mbmax).astype(np.int32)
+        ms = (sel % (w.lmax + 1)).astype(np.int32)
+        G = G_cols_fn(sel)
+        ts = time.perf_counter()
+        oracle.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, cols=(mb, ms))
+        oracle.column_sums(w.lmax, w.mbmax, x, G, (mb, ms))
+        te = time.perf_counter()
+        elapsed += te - ts
+        done_terms += 2 * int(np.sum(w.lmax + 1 - np.maximum(np.abs(mb), ms))) * w.nring
+        ncols += sel.size
+        if elapsed >= seconds:
+            break
+    return {
+        "value": done_terms / elapsed,
+        "unit": "terms/s",
+        "cores": int(oracle.max_threads()),
+        "kind": "oracle",
+        "sample": f"{ncols} seeded random (mb, msky) columns x all {w.nring} rings of the {w.name} "
+                  f"workload, forward + adjoint column sums, x87 long double, {elapsed:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import synthetic as S
+
+    w = S.WORKLOADS[args.workload]
+    if w.detectors:
+        raise SystemExit("batched workloads are timed by bench_batched")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x = w.xring()
+    alm_h, blm_h = w.alm(), w.blm()
+    alm = torch.from_numpy(alm_h).to(dev)
+    blm = torch.from_numpy(blm_h).to(dev)
+    terms = w.terms()
+    log(f"workload {w.name}: lmax={w.lmax} mbmax={w.mbmax} nring={w.nring} terms/pass={terms:.4e}")
+
+    # untimed set-up: C, the target C_T from a second sky, cotangent G = C - C_T
+    C = torch.empty((2 * w.mbmax + 1, w.lmax + 1, w.nring), dtype=torch.complex128, device=dev)
+    B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
+    T = B.totalconv_fwd(w.lmax, w.mbmax, x, torch.from_numpy(S.sky_alm(w.lmax, w.target_seed or 1050)).to(dev), blm)
+    G = C - T
+    del T
+    torch.cuda.synchronize()
+    log("set-up done")
+
+    def step():
+        B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
+        if not args.fwd_only:
+            B.totalconv_adj(w.lmax, w.mbmax, x, alm, blm, G)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    stream = torch.cuda.current_stream(dev)
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
+        e[1].record(stream)
+        if not args.fwd_only:
+            B.totalconv_adj(w.lmax, w.mbmax, x, alm, blm, G)
+        e[2].record(stream)
+        ev.append(e)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev])) if not args.fwd_only else 0.0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; forward {fwd_ms:.2f} ms, adjoint {adj_ms:.2f} ms")
+
+    passes = 1 if args.fwd_only else 2
+    ms_per_step = elapsed / args.steps * 1e3
+    value = passes * terms / (elapsed / args.steps)
+    paired = bool(np.all(x[::-1][: w.nring // 2] == -x[: w.nring // 2]))
+    fpt = FLOPS_PER_TERM_PAIRED if paired else FLOPS_PER_TERM_UNPAIRED
+    dom_name, dom_ms = ("totalconv_adj (k_adj + epilogues)", adj_ms) if adj_ms > fwd_ms else ("totalconv_fwd (k_fwd)", fwd_ms)
+    achieved = fpt * terms / (dom_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": dom_name,
+        "achieved": round(achieved, 3),
+        "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "flops_per_term": fpt,
+        "terms_per_launch": terms,
+        "launch_ms": round(dom_ms, 3),
+    }
+    result = {
+        "metric": "(l,mb,msky,beta) convolution terms/s, forward + adjoint",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"total convolution {'forward' if args.fwd_only else 'forward + adjoint'}, "
+                        f"lmax={w.lmax}, mbmax={w.mbmax}, msky 0..{w.lmax}, {w.nring} equispaced rings",
+            "lmax": w.lmax, "mbmax": w.mbmax, "nring": w.nring,
+            "terms_per_pass": terms, "passes_per_step": passes,
+        },
+        "forward_ms": round(fwd_ms, 3),
+        "adjoint_ms": round(adj_ms, 3),
+        "forward_terms_per_s": terms / (fwd_ms * 1e-3),
+        "adjoint_terms_per_s": (terms / (adj_ms * 1e-3)) if adj_ms else None,
+        "roofline": roofline,
+    }
+    if args.cpu_seconds > 0:
+        nring = w.nring
+        Gc = G.reshape(-1, nring)
+
+        def g_cols(sel):
+            idx = torch.from_numpy(np.asarray(sel, np.int64)).to(dev)
+            return Gc.index_select(0, idx).cpu().numpy()
+
+        log(f"cpu baseline: oracle on a sample, about {args.cpu_seconds:.0f} s")
+        result["cpu_baseline"] = cpu_baseline(w, x, alm_h, blm_h, g_cols, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

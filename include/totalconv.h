@@ -1,0 +1,136 @@
+/*
+ * totalconv.h -- C ABI of libtotalconv, the MI355X (gfx950) implementation of
+ * the reduced-Wigner l-recursion and the total-convolution coefficients of
+ * Prezeau & Reinecke, "Algorithm for the evaluation of reduced Wigner
+ * matrices" (arXiv:1002.1050).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - d^l_{m m'}(beta) = <l m| exp(-i beta J_y) |l m'>  (Sec. 2, eq. reducedwignerdef).
+ * - A ring is given by x = cos(beta), a double in [-1, 1] (the per-ring cos(beta)
+ *   of Sec. 4.2.2).  Rings j and nring-1-j form a mirror pair (beta, pi - beta)
+ *   when x[nring-1-j] == -x[j] exactly; such pairs share one recursion
+ *   (Sec. 4.2.3, appendix eq. pithetasym).  Any other ring is computed on its own.
+ * - Complex arrays are interleaved FP64 pairs (re, im), 16-byte aligned.
+ * - Sky ("alm"): s_{l,m} for 0 <= m <= l <= lmax, packed m-major,
+ *   index(l, m) = m*(2*lmax+1-m)/2 + l; s_{l,-m} = (-1)^m conj(s_{l,m}) is implied
+ *   (real sky, Sec. 4.2.3 eq. blmslmsym).
+ * - Beam ("blm"): [2*mbmax+1][lmax+1], row mb+mbmax holds b_{l,mb}; entries with
+ *   l < |mb| are ignored.
+ * - Coefficients ("C"): [2*mbmax+1][lmax+1][nring], element (mb, msky, j) holds
+ *   C_{mb,msky}(beta_j) for mb in [-mbmax, mbmax] and msky in [0, lmax]; the
+ *   columns with msky < 0 follow from C_{-mb,-msky} = conj(C_{mb,msky})
+ *   (Sec. 4.2.3) and are not stored.
+ *
+ * Memory, streams, errors
+ * -----------------------
+ * - Pointers marked (host) are host memory; every other pointer is device memory
+ *   of the current HIP device.  The caller owns all memory; the library never
+ *   frees a caller buffer.
+ * - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL for the
+ *   default stream) and the call returns without waiting for it, except that
+ *   the small host-computed tables are copied into the workspace on that stream
+ *   before the call returns.  Buffers must stay valid until the stream has
+ *   passed the call.
+ * - Return value 0 on success, otherwise one of the negative TC_E* codes;
+ *   tc_last_error() returns a message for the calling thread's last failure.
+ *   Invalid arguments are rejected before any GPU work is enqueued.
+ * - Results are deterministic: no floating-point atomics; the order of every
+ *   sum is fixed by the tile configuration.
+ */
+#ifndef TOTALCONV_H
+#define TOTALCONV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_OK 0
+#define TC_EINVAL (-1)        /* invalid argument                         */
+#define TC_EHIP (-2)          /* a HIP runtime call failed                */
+#define TC_ENOMEM (-3)        /* workspace too small or allocation failed */
+#define TC_EUNSUPPORTED (-4)  /* valid request this build cannot serve    */
+
+#define TC_OP_WIGNER 0
+#define TC_OP_FWD 1
+#define TC_OP_ADJ 2
+
+#define TC_LMAX_LIMIT 16384
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char* tc_last_error(void);
+
+/* ABI revision of this header. */
+int tc_abi_version(void);
+
+/*
+ * Device workspace, in bytes, that an entry point needs.
+ *   op = TC_OP_WIGNER: `mbmax` is the number of (mb, msky) pairs;
+ *   op = TC_OP_FWD / TC_OP_ADJ: the arguments of totalconv_fwd / totalconv_adj.
+ * Returns 0 for invalid arguments.
+ */
+size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring);
+
+/*
+ * As totalconv_workspace_bytes, for the given ring set (host, nring cosines):
+ * exact when the rings form mirror pairs, which need fewer ring slots than the
+ * worst case assumed above.  Returns 0 for invalid arguments.
+ */
+size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* cosbeta);
+
+/*
+ * Reduced Wigner elements by the l-recursion of Sec. 3.2 (seeds eqs. ini1..ini2
+ * at l0 = max(|mb|,|msky|) evaluated as logarithms, eq. logstart; the recursion
+ * eq. lrec in the F0/F1/F2 form of Sec. 4.2.2; exact power-of-two scaling while
+ * values are below 2^-900).
+ *   lmax         0 <= lmax <= TC_LMAX_LIMIT
+ *   npair        number of (mb, msky) pairs, >= 1
+ *   mb, msky     (host) npair integers each, |mb|, |msky| <= lmax
+ *   nring        number of rings, >= 1
+ *   cosbeta      (host) nring ring cosines in [-1, 1]
+ *   d            out: [npair][lmax+1][nring] doubles, d[i][l][j] = d^l_{mb[i],msky[i]}(beta_j),
+ *                0 for l < l0; values below the double range come out as 0 or subnormal
+ *   workspace    at least totalconv_workspace_bytes(TC_OP_WIGNER, lmax, npair, nring) bytes
+ */
+int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky,
+                   int nring, const double* cosbeta, double* d,
+                   void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Total-convolution coefficients (Sec. 4.1, eq. convdef):
+ *   C_{mb,msky}(beta_j) = sum_{l=l0}^{lmax} conj(b_{l,mb}) d^l_{mb,msky}(beta_j) s_{l,msky}.
+ * Terms whose |d| stays below 2^-100 (about the paper's 1e-30) before the first
+ * crossing of that threshold within a 64-lane group of rings may be left out of
+ * the sum (Sec. 4.2.1); the recursion itself always runs over every l.
+ *   lmax, mbmax  0 <= mbmax <= lmax <= TC_LMAX_LIMIT
+ *   nring        >= 1;  cosbeta (host) nring ring cosines in [-1, 1]
+ *   alm          sky, (lmax+1)(lmax+2)/2 complex
+ *   blm          beam, (2*mbmax+1)*(lmax+1) complex
+ *   C            out: (2*mbmax+1)*(lmax+1)*nring complex
+ *   workspace    at least totalconv_workspace_bytes(TC_OP_FWD, lmax, mbmax, nring) bytes
+ */
+int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta,
+                  const double* alm, const double* blm, double* C,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of totalconv_fwd (not in the paper; the exact transpose of eq. convdef).
+ * With Cbar = dL/dconj(C) (the layout of C; PyTorch's gradient convention),
+ *   alm_bar_{l,msky} = sum_{mb,j} b_{l,mb} d^l_{mb,msky}(beta_j) Cbar_{mb,msky,j}
+ *   blm_bar_{l,mb}   = sum_{msky,j} s_{l,msky} d^l_{mb,msky}(beta_j) conj(Cbar_{mb,msky,j})
+ * d is recomputed on the fly.  alm_bar (layout of alm) and blm_bar (layout of blm)
+ * may each be NULL; blm_bar entries with l < |mb| are written as 0.
+ *   workspace    at least totalconv_workspace_bytes(TC_OP_ADJ, lmax, mbmax, nring) bytes
+ */
+int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
+                  const double* alm, const double* blm, const double* Cbar,
+                  double* alm_bar, double* blm_bar,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOTALCONV_H */

@@ -1,0 +1,186 @@
+"""ctypes binding of libtotalconv (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch tensors
+and numpy arrays into the pointers, sizes and stream handle the C ABI expects
+(include/totalconv.h), allocates the device workspace with torch, and turns a
+non-zero status into an exception.  If the built library is missing it raises;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtotalconv.so")
+
+TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ = 0, 1, 2
+TC_LMAX_LIMIT = 16384
+
+_lib = None
+_lock = threading.Lock()
+
+
+class TotalConvError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libtotalconv.so (built in-tree by paper_1002_1050_amd/build.py)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is not built; run `python -m paper_1002_1050_amd.build` "
+                    "(there is no CPU fallback)")
+            L = ctypes.CDLL(LIB_PATH)
+            I, P, S = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+            L.tc_last_error.restype = ctypes.c_char_p
+            L.tc_last_error.argtypes = []
+            L.tc_abi_version.restype = I
+            L.tc_abi_version.argtypes = []
+            L.totalconv_workspace_bytes.restype = S
+            L.totalconv_workspace_bytes.argtypes = [I, I, I, I]
+            L.totalconv_workspace_bytes_rings.restype = S
+            L.totalconv_workspace_bytes_rings.argtypes = [I, I, I, I, P]
+            L.wigner_d_rings.restype = I
+            L.wigner_d_rings.argtypes = [I, I, P, P, I, P, P, P, S, P]
+            L.totalconv_fwd.restype = I
+            L.totalconv_fwd.argtypes = [I, I, I, P, P, P, P, P, S, P]
+            L.totalconv_adj.restype = I
+            L.totalconv_adj.argtypes = [I, I, I, P, P, P, P, P, P, P, S, P]
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().tc_last_error().decode()
+
+
+def _check(fn: str, rc: int):
+    if rc != 0:
+        raise TotalConvError(fn, rc, last_error())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_device(t, name, dtype):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class _Workspace:
+    """Grow-only device workspace per (device, stream)."""
+
+    def __init__(self):
+        self._bufs = {}
+
+    def get(self, torch, device, stream, nbytes):
+        key = (device.index, stream.value)
+        buf = self._bufs.get(key)
+        if buf is None or buf.numel() < nbytes:
+            self._bufs.pop(key, None)
+            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self._bufs[key] = buf
+        return buf
+
+    def clear(self):
+        self._bufs.clear()
+
+
+workspace_cache = _Workspace()
+
+
+def workspace_bytes(op: int, lmax: int, mbmax: int, cosbeta) -> int:
+    """Exact workspace size for this ring set; 0 when the arguments are invalid (the entry
+    point itself then reports why)."""
+    x = _host(cosbeta, np.float64)
+    return int(lib().totalconv_workspace_bytes_rings(op, lmax, mbmax, x.size, _hptr(x)))
+
+
+def wigner_d_rings(lmax: int, mb, msky, cosbeta, device="cuda"):
+    """d^l_{mb[i],msky[i]}(beta_j) on the GPU, shape (npair, lmax+1, nring) float64."""
+    import torch
+    device = torch.device(device)
+    mb = _host(np.atleast_1d(mb), np.int32)
+    ms = _host(np.atleast_1d(msky), np.int32)
+    x = _host(np.atleast_1d(cosbeta), np.float64)
+    if mb.shape != ms.shape:
+        raise ValueError("mb and msky must have the same length")
+    out = torch.empty((mb.size, lmax + 1, x.size), dtype=torch.float64, device=device)
+    nbytes = lib().totalconv_workspace_bytes(TC_OP_WIGNER, lmax, max(mb.size, 1), max(x.size, 1))
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, nbytes)
+    rc = lib().wigner_d_rings(lmax, mb.size, _hptr(mb), _hptr(ms), x.size, _hptr(x), _dptr(out),
+                              _dptr(ws), ws.numel(), stream)
+    _check("wigner_d_rings", rc)
+    return out
+
+
+def totalconv_fwd(lmax: int, mbmax: int, cosbeta, alm, blm, out=None):
+    """C = totalconv(alm, blm) on the rings cosbeta; complex128 (2*mbmax+1, lmax+1, nring)."""
+    import torch
+    _require_device(alm, "alm", torch.complex128)
+    _require_device(blm, "blm", torch.complex128)
+    device = alm.device
+    x = _host(cosbeta, np.float64)
+    if alm.numel() != (lmax + 1) * (lmax + 2) // 2 or blm.numel() != (2 * mbmax + 1) * (lmax + 1):
+        raise ValueError("alm / blm sizes do not match lmax / mbmax")
+    shape = (2 * mbmax + 1, lmax + 1, x.size)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex128, device=device)
+    else:
+        _require_device(out, "out", torch.complex128)
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {shape}")
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, workspace_bytes(TC_OP_FWD, lmax, mbmax, x))
+    rc = lib().totalconv_fwd(lmax, mbmax, x.size, _hptr(x), _dptr(alm), _dptr(blm), _dptr(out),
+                             _dptr(ws), ws.numel(), stream)
+    _check("totalconv_fwd", rc)
+    return out
+
+
+def totalconv_adj(lmax: int, mbmax: int, cosbeta, alm, blm, Cbar, want_alm=True, want_blm=True):
+    """(alm_bar, blm_bar) for the cotangent Cbar = dL/dconj(C); either may be None."""
+    import torch
+    for t, n in ((alm, "alm"), (blm, "blm"), (Cbar, "Cbar")):
+        _require_device(t, n, torch.complex128)
+    device = alm.device
+    x = _host(cosbeta, np.float64)
+    if Cbar.numel() != (2 * mbmax + 1) * (lmax + 1) * x.size:
+        raise ValueError("Cbar size does not match (2*mbmax+1, lmax+1, nring)")
+    alm_bar = torch.empty_like(alm) if want_alm else None
+    blm_bar = torch.empty_like(blm) if want_blm else None
+    if not want_alm and not want_blm:
+        return None, None
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, workspace_bytes(TC_OP_ADJ, lmax, mbmax, x))
+    rc = lib().totalconv_adj(lmax, mbmax, x.size, _hptr(x), _dptr(alm), _dptr(blm), _dptr(Cbar),
+                             _dptr(alm_bar), _dptr(blm_bar), _dptr(ws), ws.numel(), stream)
+    _check("totalconv_adj", rc)
+    return alm_bar, blm_bar

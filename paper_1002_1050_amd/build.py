@@ -1,0 +1,52 @@
+"""Build libtotalconv.so in-tree for gfx950.
+
+hipcc compiles the kernels (tc_kernels.hip); the host-side tables and C entry
+points (tc_host.cpp) are plain C++ built with g++ against the HIP runtime
+headers; hipcc links both into paper_1002_1050_amd/libtotalconv.so.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libtotalconv.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = "gfx950"
+
+HIP_FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
+    # packed FP32 instructions stay off (no FP32 arithmetic here, and the forms are avoided)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    hipcc = os.path.join(ROCM, "bin", "hipcc")
+    k_obj = os.path.join(BUILD, "tc_kernels.o")
+    h_obj = os.path.join(BUILD, "tc_host.o")
+    _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_kernels.hip"), "-o", k_obj])
+    _run(["g++", "-O2", "-fPIC", "-std=c++17", "-Wall", "-D__HIP_PLATFORM_AMD__",
+          "-I", os.path.join(ROCM, "include"), *inc, "-c", os.path.join(CSRC, "tc_host.cpp"), "-o", h_obj])
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, h_obj,
+          "-L", os.path.join(ROCM, "lib"), "-lamdhip64"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,377 @@
+// Host side of libtotalconv: argument checks, the small per-call tables
+// (built in x87 long double and stored as double or double-double), the
+// workspace layout and the extern "C" entry points declared in totalconv.h.
+//
+// Tables (Sec. 4.2.2 of Prezeau & Reinecke, "compute just once"):
+//   per ring  j: x_j = cos(beta_j), ln cos(beta_j/2), ln sin(beta_j/2)
+//   per column : ln A = ln sqrt((2 l0)! / ((l0+m)! (l0-m)!)), the seed normalisation
+//                of Sec. 3.2 eq. logstart, with ln n! from lgammal
+//   ring slots : mirror pairs (j, nring-1-j) with x exactly negated, then the rest
+//   column list: every (mb, msky) column, longest chains (smallest l0) first
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/totalconv.h"
+#include "tc_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(int rc, const char* what)
+{
+    return fail(TC_EHIP, "%s: %s", what, hipGetErrorString((hipError_t)rc));
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+typedef long double ld;
+
+void split_dd(ld v, double& hi, double& lo)
+{
+    hi = (double)v;
+    lo = std::isinf(hi) ? 0.0 : (double)(v - (ld)hi);
+}
+
+// ---------------------------------------------------------------- tile choice
+
+tc::Tile default_tile(int op, int lmax)
+{
+    const char* env = nullptr;
+    if (op == TC_OP_WIGNER) env = std::getenv("TC_TILE_WIGNER_R");
+    if (op == TC_OP_FWD) env = std::getenv("TC_TILE_FWD_R");
+    if (op == TC_OP_ADJ) env = std::getenv("TC_TILE_ADJ_R");
+    tc::Tile t{op == TC_OP_WIGNER ? 4 : (lmax >= 256 ? 8 : 2), 256};
+    if (env && *env) {
+        tc::Tile e{std::atoi(env), 256};
+        if (tc::tile_supported(op, e)) t = e;
+    }
+    return t;
+}
+
+// ------------------------------------------------------------- table layout
+
+struct Layout {
+    size_t ring = 0, slots = 0, colmb = 0, colms = 0, lna = 0, tables_end = 0;
+    size_t U = 0, V = 0, total = 0;
+    int nslot = 0, ncol = 0, ntile = 0;
+    long long P = 0;
+};
+
+int count_slots(int nring, const double* x)
+{
+    if (!x) return nring;   // size queries: at most nring slots
+    int n = 0;
+    for (int j = 0; j < nring; ++j) {
+        const int jp = nring - 1 - j;
+        if (j < jp && x[jp] == -x[j]) ++n;          // pair (j, jp)
+        else if (j > jp && x[j] == -x[jp]) continue;  // partner of an earlier pair
+        else ++n;                                   // single ring
+    }
+    return n;
+}
+
+Layout make_layout(int op, int lmax, int mbmax_or_npair, int nring, const double* x, tc::Tile t)
+{
+    Layout L;
+    const bool conv = op != TC_OP_WIGNER;
+    L.nslot = conv ? count_slots(nring, x) : nring;
+    L.ncol = conv ? (2 * mbmax_or_npair + 1) * (lmax + 1) : mbmax_or_npair;
+    L.ntile = (L.nslot + t.NT * t.R - 1) / (t.NT * t.R);
+    size_t off = 0;
+    L.ring = off;  off = align_up(off + sizeof(double) * 5 * (size_t)nring);
+    L.slots = off; off = align_up(off + sizeof(int) * 2 * (size_t)L.nslot);
+    L.colmb = off; off = align_up(off + sizeof(int) * (size_t)L.ncol);
+    L.colms = off; off = align_up(off + sizeof(int) * (size_t)L.ncol);
+    L.lna = off;   off = align_up(off + sizeof(double) * 2 * (size_t)L.ncol);
+    L.tables_end = off;
+    if (op == TC_OP_ADJ) {
+        L.P = (long long)(lmax + 1) * (lmax + 2) / 2;
+        const size_t ubytes = (size_t)16 * (size_t)L.ntile * (size_t)(2 * mbmax_or_npair + 1) * (size_t)L.P;
+        L.U = off; off = align_up(off + ubytes);
+        L.V = off; off = align_up(off + ubytes);
+    }
+    L.total = off;
+    return L;
+}
+
+// Seed normalisation index m of column (mb, ms) at l0 = max(|mb|, |ms|).
+int seed_m(int mb, int ms) { return std::abs(ms) >= std::abs(mb) ? mb : ms; }
+
+ld ln_A(int mb, int ms)
+{
+    const int l0 = std::max(std::abs(mb), std::abs(ms));
+    const int m = seed_m(mb, ms);
+    return 0.5L * (lgammal((ld)(2 * l0 + 1)) - lgammal((ld)(l0 + m + 1)) - lgammal((ld)(l0 - m + 1)));
+}
+
+// Fill the table part of the workspace image.
+void build_rings(int nring, const double* x, std::vector<char>& img, const Layout& L)
+{
+    double* r = reinterpret_cast<double*>(img.data() + L.ring);
+    double *rx = r, *lch = r + nring, *lcl = r + 2 * nring, *lsh = r + 3 * nring, *lsl = r + 4 * nring;
+    for (int j = 0; j < nring; ++j) {
+        const ld X = (ld)x[j];
+        const ld c2 = (1.0L + X) / 2.0L;   // cos^2(beta/2)
+        const ld s2 = (1.0L - X) / 2.0L;   // sin^2(beta/2)
+        ld lc, ls;
+        if (c2 == 0.0L) lc = -INFINITY;
+        else lc = 0.5L * (X > 0 ? log1pl(-s2) : logl(c2));
+        if (s2 == 0.0L) ls = -INFINITY;
+        else ls = 0.5L * (X < 0 ? log1pl(-c2) : logl(s2));
+        rx[j] = x[j];
+        split_dd(lc, lch[j], lcl[j]);
+        split_dd(ls, lsh[j], lsl[j]);
+    }
+}
+
+void build_slots(int nring, const double* x, std::vector<char>& img, const Layout& L)
+{
+    int* s = reinterpret_cast<int*>(img.data() + L.slots);
+    int n = 0;
+    std::vector<int> single;
+    for (int j = 0; j < nring; ++j) {
+        const int jp = nring - 1 - j;
+        if (j < jp && x[jp] == -x[j]) { s[2 * n] = j; s[2 * n + 1] = jp; ++n; }
+        else if (j > jp && x[j] == -x[jp]) continue;
+        else single.push_back(j);
+    }
+    for (int j : single) { s[2 * n] = j; s[2 * n + 1] = -1; ++n; }
+}
+
+void build_columns(int lmax, int mbmax, std::vector<char>& img, const Layout& L)
+{
+    struct Col { int mb, ms, l0; };
+    std::vector<Col> cols;
+    cols.reserve(L.ncol);
+    for (int mb = -mbmax; mb <= mbmax; ++mb)
+        for (int ms = 0; ms <= lmax; ++ms)
+            cols.push_back({mb, ms, std::max(std::abs(mb), ms)});
+    std::stable_sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) { return a.l0 < b.l0; });
+    int* cmb = reinterpret_cast<int*>(img.data() + L.colmb);
+    int* cms = reinterpret_cast<int*>(img.data() + L.colms);
+    double* lna = reinterpret_cast<double*>(img.data() + L.lna);
+    for (int i = 0; i < L.ncol; ++i) {
+        cmb[i] = cols[i].mb;
+        cms[i] = cols[i].ms;
+        split_dd(ln_A(cols[i].mb, cols[i].ms), lna[2 * i], lna[2 * i + 1]);
+    }
+}
+
+void build_pairs(int npair, const int* mb, const int* ms, std::vector<char>& img, const Layout& L)
+{
+    int* cmb = reinterpret_cast<int*>(img.data() + L.colmb);
+    int* cms = reinterpret_cast<int*>(img.data() + L.colms);
+    double* lna = reinterpret_cast<double*>(img.data() + L.lna);
+    for (int i = 0; i < npair; ++i) {
+        cmb[i] = mb[i];
+        cms[i] = ms[i];
+        split_dd(ln_A(mb[i], ms[i]), lna[2 * i], lna[2 * i + 1]);
+    }
+}
+
+int check_rings(int nring, const double* x)
+{
+    if (nring < 1) return fail(TC_EINVAL, "nring must be >= 1 (got %d)", nring);
+    if (!x) return fail(TC_EINVAL, "cosbeta is NULL");
+    for (int j = 0; j < nring; ++j)
+        if (!(x[j] >= -1.0 && x[j] <= 1.0))
+            return fail(TC_EINVAL, "cosbeta[%d] = %g is not a ring cosine in [-1, 1]", j, x[j]);
+    return TC_OK;
+}
+
+int check_sizes(int lmax, int mbmax)
+{
+    if (lmax < 0 || lmax > TC_LMAX_LIMIT)
+        return fail(TC_EINVAL, "lmax = %d outside [0, %d]", lmax, TC_LMAX_LIMIT);
+    if (mbmax < 0 || mbmax > lmax)
+        return fail(TC_EINVAL, "mbmax = %d outside [0, lmax = %d]", mbmax, lmax);
+    return TC_OK;
+}
+
+int check_ws(const Layout& L, void* ws, size_t ws_bytes)
+{
+    if (ws_bytes < L.total)
+        return fail(TC_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, L.total);
+    if (!ws) return fail(TC_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return fail(TC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    return TC_OK;
+}
+
+int upload(void* ws, const std::vector<char>& img, void* stream)
+{
+    const int rc = (int)hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    return rc ? hip_fail(rc, "table upload (hipMemcpyAsync)") : TC_OK;
+}
+
+tc::RingTables ring_ptrs(void* ws, const Layout& L, int nring)
+{
+    const double* r = reinterpret_cast<const double*>(static_cast<char*>(ws) + L.ring);
+    return tc::RingTables{r, r + nring, r + 2 * nring, r + 3 * nring, r + 4 * nring};
+}
+
+tc::ColumnTables col_ptrs(void* ws, const Layout& L)
+{
+    char* b = static_cast<char*>(ws);
+    return tc::ColumnTables{reinterpret_cast<const int*>(b + L.colmb), reinterpret_cast<const int*>(b + L.colms),
+                            reinterpret_cast<const double*>(b + L.lna)};
+}
+
+int check_grid(const Layout& L)
+{
+    if ((long long)L.ncol * L.ntile > 0x7fffffffLL)
+        return fail(TC_EUNSUPPORTED, "launch of %lld workgroups exceeds the grid limit", (long long)L.ncol * L.ntile);
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tc_last_error(void) { return g_error.c_str(); }
+
+int tc_abi_version(void) { return 1; }
+
+size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring)
+{
+    if (nring < 1 || lmax < 0 || lmax > TC_LMAX_LIMIT) return 0;
+    if (op == TC_OP_WIGNER) {
+        if (mbmax < 1) return 0;
+    } else if (op == TC_OP_FWD || op == TC_OP_ADJ) {
+        if (mbmax < 0 || mbmax > lmax) return 0;
+    } else {
+        return 0;
+    }
+    return make_layout(op, lmax, mbmax, nring, nullptr, default_tile(op, lmax)).total;
+}
+
+size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* cosbeta)
+{
+    if (!cosbeta || totalconv_workspace_bytes(op, lmax, mbmax, nring) == 0) return 0;
+    for (int j = 0; j < nring; ++j)
+        if (!(cosbeta[j] >= -1.0 && cosbeta[j] <= 1.0)) return 0;
+    return make_layout(op, lmax, mbmax, nring, cosbeta, default_tile(op, lmax)).total;
+}
+
+int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nring, const double* cosbeta,
+                   double* d, void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    if (lmax < 0 || lmax > TC_LMAX_LIMIT) return fail(TC_EINVAL, "lmax = %d outside [0, %d]", lmax, TC_LMAX_LIMIT);
+    if (npair < 1) return fail(TC_EINVAL, "npair must be >= 1 (got %d)", npair);
+    if (!mb || !msky) return fail(TC_EINVAL, "mb / msky is NULL");
+    for (int i = 0; i < npair; ++i)
+        if (std::abs(mb[i]) > lmax || std::abs(msky[i]) > lmax)
+            return fail(TC_EINVAL, "pair %d: |mb| = %d or |msky| = %d exceeds lmax = %d", i, std::abs(mb[i]),
+                        std::abs(msky[i]), lmax);
+    int rc = check_rings(nring, cosbeta);
+    if (rc) return rc;
+    if (!d) return fail(TC_EINVAL, "d is NULL");
+    const tc::Tile t = default_tile(TC_OP_WIGNER, lmax);
+    const Layout L = make_layout(TC_OP_WIGNER, lmax, npair, nring, cosbeta, t);
+    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
+    std::vector<char> img(L.tables_end, 0);
+    build_rings(nring, cosbeta, img, L);
+    build_pairs(npair, mb, msky, img, L);
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::WignerArgs a{};
+    a.lmax = lmax; a.npair = npair; a.nring = nring; a.ntile = L.ntile;
+    a.ring = ring_ptrs(workspace, L, nring);
+    a.col = col_ptrs(workspace, L);
+    a.d = d;
+    rc = tc::launch_wigner(a, t, stream);
+    return rc ? hip_fail(rc, "wigner_d_rings launch") : TC_OK;
+}
+
+int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
+                  double* C, void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    int rc = check_sizes(lmax, mbmax);
+    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
+    if (!alm || !blm || !C) return fail(TC_EINVAL, "alm, blm or C is NULL");
+    if (!aligned16(alm) || !aligned16(blm) || !aligned16(C))
+        return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+    const tc::Tile t = default_tile(TC_OP_FWD, lmax);
+    const Layout L = make_layout(TC_OP_FWD, lmax, mbmax, nring, cosbeta, t);
+    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
+    std::vector<char> img(L.tables_end, 0);
+    build_rings(nring, cosbeta, img, L);
+    build_slots(nring, cosbeta, img, L);
+    build_columns(lmax, mbmax, img, L);
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::FwdArgs a{};
+    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
+    a.skip_exp = 100;
+    a.ring = ring_ptrs(workspace, L, nring);
+    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
+    a.col = col_ptrs(workspace, L);
+    a.alm = alm; a.blm = blm; a.C = C;
+    rc = tc::launch_fwd(a, t, stream);
+    return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
+}
+
+int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
+                  const double* Cbar, double* alm_bar, double* blm_bar, void* workspace, size_t ws_bytes,
+                  void* stream)
+{
+    g_error.clear();
+    int rc = check_sizes(lmax, mbmax);
+    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
+    if (!alm || !blm || !Cbar) return fail(TC_EINVAL, "alm, blm or Cbar is NULL");
+    if (!aligned16(alm) || !aligned16(blm) || !aligned16(Cbar) || (alm_bar && !aligned16(alm_bar)) ||
+        (blm_bar && !aligned16(blm_bar)))
+        return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+    if (!alm_bar && !blm_bar) return TC_OK;   // nothing requested
+    const tc::Tile t = default_tile(TC_OP_ADJ, lmax);
+    const Layout L = make_layout(TC_OP_ADJ, lmax, mbmax, nring, cosbeta, t);
+    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
+    std::vector<char> img(L.tables_end, 0);
+    build_rings(nring, cosbeta, img, L);
+    build_slots(nring, cosbeta, img, L);
+    build_columns(lmax, mbmax, img, L);
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::AdjArgs a{};
+    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
+    a.skip_exp = 100;
+    a.ring = ring_ptrs(workspace, L, nring);
+    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
+    a.col = col_ptrs(workspace, L);
+    a.Cbar = Cbar;
+    a.U = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
+    a.V = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
+    a.P = L.P;
+    rc = tc::launch_adj(a, t, stream);
+    if (rc) return hip_fail(rc, "totalconv_adj launch");
+    tc::EpiArgs e{};
+    e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P;
+    e.U = a.U; e.V = a.V; e.alm = alm; e.blm = blm; e.alm_bar = alm_bar; e.blm_bar = blm_bar;
+    rc = tc::launch_adj_epilogue(e, stream);
+    return rc ? hip_fail(rc, "totalconv_adj epilogue launch") : TC_OK;
+}
+
+}  // extern "C"

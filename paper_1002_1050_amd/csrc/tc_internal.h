@@ -1,0 +1,82 @@
+// Internal declarations of libtotalconv shared by the host-side table builder
+// (tc_host.cpp) and the gfx950 kernels (tc_kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tc {
+
+// Launch shape of the recursion kernels: each lane owns R chains (rings) of one
+// (mb, msky) column and a workgroup has NT lanes, so one workgroup covers
+// NT*R ring slots of one column.
+struct Tile {
+    int R;    // chains per lane
+    int NT;   // lanes per workgroup
+};
+
+// Device-resident per-call tables, all inside the caller's workspace.
+struct RingTables {
+    const double* x;     // cos(beta_j)
+    const double* lch;   // ln cos(beta_j/2), double-double (hi, lo); hi = -inf when cos(beta_j/2) = 0
+    const double* lcl;
+    const double* lsh;   // ln sin(beta_j/2), double-double; hi = -inf when sin(beta_j/2) = 0
+    const double* lsl;
+};
+
+// Column list (processing order) with the seed normalisation of each column.
+struct ColumnTables {
+    const int* mb;       // [ncol]
+    const int* ms;       // [ncol]
+    const double* lnA;   // [ncol][2] double-double ln sqrt((2l0)!/((l0+m)!(l0-m)!))
+};
+
+struct WignerArgs {
+    int lmax, npair, nring, ntile;
+    RingTables ring;
+    ColumnTables col;      // one "column" per requested (mb, msky) pair, in request order
+    double* d;             // [npair][lmax+1][nring]
+};
+
+struct FwdArgs {
+    int lmax, mbmax, nring, nslot, ncol, ntile;
+    int skip_exp;          // accumulate from the first l-block that may hold |d| >= 2^-skip_exp; 0 = always
+    RingTables ring;
+    const int* slots;      // [nslot][2] (ring j, mirror ring or -1)
+    ColumnTables col;
+    const double* alm;     // packed sky (complex)
+    const double* blm;     // [2M+1][L+1] complex
+    double* C;             // [2M+1][L+1][nring] complex
+};
+
+struct AdjArgs {
+    int lmax, mbmax, nring, nslot, ncol, ntile;
+    int skip_exp;
+    RingTables ring;
+    const int* slots;
+    ColumnTables col;
+    const double* Cbar;    // layout of C
+    double* U;             // complex [ntile][2M+1][P] direct-ring partial sums u_l
+    double* V;             // complex [ntile][2M+1][P] mirror-ring partial sums (before the (-1)^(l-msky) sign)
+    long long P;           // (L+1)(L+2)/2
+};
+
+struct EpiArgs {
+    int lmax, mbmax, ntile;
+    long long P;
+    const double* U;
+    const double* V;
+    const double* alm;
+    const double* blm;
+    double* alm_bar;       // may be null
+    double* blm_bar;       // may be null
+};
+
+// Kernel launchers (tc_kernels.hip).  Return a hipError_t value (0 on success).
+int launch_wigner(const WignerArgs& a, Tile t, void* stream);
+int launch_fwd(const FwdArgs& a, Tile t, void* stream);
+int launch_adj(const AdjArgs& a, Tile t, void* stream);
+int launch_adj_epilogue(const EpiArgs& e, void* stream);
+bool tile_supported(int op, Tile t);
+
+}  // namespace tc

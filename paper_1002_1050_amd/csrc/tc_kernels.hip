@@ -1,0 +1,718 @@
+// gfx950 kernels of libtotalconv: reduced Wigner elements by the l-recursion
+// and the total-convolution sum with its adjoint (Prezeau & Reinecke,
+// arXiv:1002.1050, Secs. 3.2 and 4).
+//
+// Mapping.  A workgroup owns one (mb, msky) column and NT*R ring slots of it;
+// each lane walks R chains (one per ring slot) up in l, in lock-step, so the
+// per-l recursion coefficients and weights are uniform across the workgroup.
+// They are built per block of TB values of l in LDS (double-buffered: the next
+// block is prepared while the current one is consumed) and read back as
+// broadcasts.  A ring slot is either a mirror pair (beta, pi - beta) -- one
+// recursion serves both rings through d^l_{-mb,msky}(pi-beta) =
+// (-1)^(l-msky) d^l_{mb,msky}(beta) (appendix eq. pithetasym) -- or a single ring.
+//
+// Numbers.  Everything is FP64.  The seed at l0 = max(|mb|,|msky|) is formed
+// as a logarithm in double-double (Sec. 3.2 eq. logstart) and split into a
+// significand and a power of two.  While a chain's value is below 2^-900 it is
+// carried as d * 2^E with E < 0 and renormalised by exact powers of two every
+// TS steps; once it reaches 2^-900 it is folded into a plain double (E = 0),
+// as Sec. 3.2 prescribes.  The checks are wave-uniform branches, so the inner
+// loop has no per-step branches.
+
+#include <hip/hip_runtime.h>
+
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+constexpr int TB = 32;        // l values per coefficient block
+constexpr int TS = 8;         // steps between scale / skip checks
+constexpr int TR = 4;         // adjoint: steps per workgroup reduction of the lane sums
+constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-900
+// A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
+// (F0 <= l+1, |x - F1| < 2, F2 <= 2), which bounds growth inside a TS block.
+constexpr int GROWTH_BITS_PER_STEP = 16;
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// ------------------------------------------------------------- double-double
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    e = b - (s - a);
+}
+
+// (sh, sl) += n * (ah + al), n an integer held exactly in a double
+__device__ __forceinline__ void dd_add_times(double& sh, double& sl, double n, double ah, double al)
+{
+    const double ph = n * ah;
+    const double pl = fma(n, ah, -ph) + n * al;
+    double s, e;
+    two_sum(sh, ph, s, e);
+    e += sl + pl;
+    fast_two_sum(s, e, sh, sl);
+}
+
+__device__ __forceinline__ void dd_mul(double ah, double al, double bh, double bl, double& yh, double& yl)
+{
+    const double p = ah * bh;
+    const double e = fma(ah, bh, -p) + (ah * bl + al * bh);
+    fast_two_sum(p, e, yh, yl);
+}
+
+// --------------------------------------------------------------------- seeds
+// Seed d^{l0}_{mb,ms} = A c^p (+-s)^q at l0 = max(|mb|,|ms|), c = cos(beta/2),
+// s = sin(beta/2) (Sec. 3.2 eqs. ini1..ini2; the printed row labels are read as
+// d_{l,m}, d_{-l,m}, d_{m,l}, d_{m,-l}).
+struct SeedShape {
+    int p, q;
+    bool neg;
+};
+
+__device__ __forceinline__ SeedShape seed_shape(int mb, int ms)
+{
+    const int amb = abs(mb), ams = abs(ms);
+    const int l0 = max(amb, ams);
+    SeedShape s;
+    if (ams >= amb) {
+        if (ms >= 0) { s.p = l0 + mb; s.q = l0 - mb; s.neg = false; }   // d_{m,l}
+        else         { s.p = l0 - mb; s.q = l0 + mb; s.neg = (s.q & 1); }  // d_{m,-l}
+    } else {
+        if (mb > 0)  { s.p = l0 + ms; s.q = l0 - ms; s.neg = (s.q & 1); }  // d_{l,m}
+        else         { s.p = l0 - ms; s.q = l0 + ms; s.neg = false; }   // d_{-l,m}
+    }
+    return s;
+}
+
+// ln|d| = lnA + p ln c + q ln s in double-double, then d = 2^f * 2^k.
+// Returns the value in (d, E) form: E = 0 and d plain when |d| >= 2^-900,
+// otherwise d in [1, 2) and E = k < 0.  A zero base with a positive power gives
+// the zero chain (Sec. 3.2, the -infinity case).
+__device__ __forceinline__ void seed_value(double lnAh, double lnAl, SeedShape sh,
+                                           double lch, double lcl, double lsh, double lsl,
+                                           double& d, int& E)
+{
+    if ((sh.p > 0 && __builtin_isinf(lch)) || (sh.q > 0 && __builtin_isinf(lsh))) {
+        d = 0.0;
+        E = 0;
+        return;
+    }
+    double h = lnAh, lo = lnAl;
+    if (sh.p > 0) dd_add_times(h, lo, (double)sh.p, lch, lcl);
+    if (sh.q > 0) dd_add_times(h, lo, (double)sh.q, lsh, lsl);
+    double yh, yl;
+    dd_mul(h, lo, 0x1.71547652b82fep+0, 0x1.777d0ffda0d24p-56, yh, yl);   // ln -> log2
+    const double k = floor(yh);
+    const double f = (yh - k) + yl;
+    const double m = exp2(f);
+    const int ik = (int)k;
+    if (ik >= FOLD_EXP) {
+        d = ldexp(m, ik);
+        E = 0;
+    } else {
+        d = m;
+        E = ik;
+    }
+    if (sh.neg) d = -d;
+}
+
+// ------------------------------------------------------ recursion coefficients
+// d^{l+1} = F0_l (x - F1_l) d^l - F2_l d^{l-1}  (Sec. 4.2.2), evaluated as
+// fma(x, A, nB) * d^l - F2 d^{l-1} with A = F0, nB = -F0 F1.  F0 and F2 come from
+// their closed forms; at l = lmax (and beyond) the step is switched off.
+__device__ __forceinline__ void recursion_coefs(int l, int mb, int ms, int lmax,
+                                                double& A, double& nB, double& F2)
+{
+    if (l >= lmax) {
+        A = 0.0; nB = 0.0; F2 = 0.0;
+        return;
+    }
+    const double l1 = (double)(l + 1);
+    const double b2 = (double)mb * (double)mb, s2 = (double)ms * (double)ms;
+    const double den = sqrt(l1 * l1 - b2) * sqrt(l1 * l1 - s2);
+    A = l1 * (2.0 * (double)l + 1.0) / den;
+    if (l == 0) {           // F1_0 = F2_0 = 0 (only the (0,0) chain reaches l = 0)
+        nB = 0.0;
+        F2 = 0.0;
+        return;
+    }
+    const double ll = (double)l;
+    const double F1 = ((double)mb * (double)ms) / (ll * l1);
+    nB = -(A * F1);
+    F2 = (l1 * (sqrt(ll * ll - b2) * sqrt(ll * ll - s2))) / (ll * den);
+}
+
+// Exact power-of-two rescale of one chain (and the values tied to it).
+__device__ __forceinline__ int chain_exponent(double d, double dp)
+{
+    int e1, e2;
+    frexp(d, &e1);
+    frexp(dp, &e2);
+    return max(e1, e2);
+}
+
+// Renormalise a scaled chain (E < 0): fold into plain doubles once the true
+// value reaches 2^-900, else bring the significand back near 1.  Returns the
+// power of two applied to (d, dp) so the caller can apply it to its sums.
+__device__ __forceinline__ int renorm(double& d, double& dp, int& E)
+{
+    if (E >= 0) return 0;
+    const int e = chain_exponent(d, dp);
+    int k;
+    if (d == 0.0 && dp == 0.0) {
+        k = 0;
+    } else if (E + e >= FOLD_EXP) {
+        k = E;
+        E = 0;
+    } else {
+        k = -e;
+        E += e;
+    }
+    d = ldexp(d, k);
+    dp = ldexp(dp, k);
+    return k;
+}
+
+// Could |d| reach 2^-eps_exp within the next TS steps?  (True exponent E + e
+// plus the growth bound.)
+__device__ __forceinline__ bool chain_hot(double d, double dp, int E, int skip_exp)
+{
+    if (d == 0.0 && dp == 0.0) return false;
+    const int e = chain_exponent(d, dp);
+    return E + e + GROWTH_BITS_PER_STEP * TS > -skip_exp;
+}
+
+__device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
+{
+    return (size_t)m * (size_t)(2 * lmax + 1 - m) / 2 + (size_t)l;
+}
+
+// ================================================================ wigner_d_rings
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
+{
+    __shared__ double4 cf[2][TB];
+    const int tid = threadIdx.x;
+    const int pair = blockIdx.x / a.ntile;
+    const int tile = blockIdx.x - pair * a.ntile;
+    const int mb = a.col.mb[pair], ms = a.col.ms[pair];
+    const int L = a.lmax;
+    const int l0 = max(abs(mb), abs(ms));
+    const SeedShape sh = seed_shape(mb, ms);
+    const double lnAh = a.col.lnA[2 * pair], lnAl = a.col.lnA[2 * pair + 1];
+    double* const out = a.d + (size_t)pair * (size_t)(L + 1) * (size_t)a.nring;
+
+    double x[R], d[R], dp[R];
+    int E[R], jj[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = tile * (NT * R) + r * NT + tid;
+        jj[r] = j < a.nring ? j : -1;
+        x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
+        if (jj[r] >= 0) {
+            x[r] = a.ring.x[j];
+            seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
+            for (int l = 0; l < l0; ++l) out[(size_t)l * a.nring + j] = 0.0;
+        }
+    }
+    bool scaled = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
+    scaled = wave_any(scaled);
+
+    if (tid < TB) {
+        double A, nB, F2;
+        recursion_coefs(l0 + tid, mb, ms, L, A, nB, F2);
+        cf[0][tid] = make_double4(A, nB, F2, 0.0);
+    }
+    __syncthreads();
+    const int nblk = (L - l0) / TB + 1;
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int buf = kb & 1;
+        const int lb = l0 + kb * TB;
+        for (int s0 = 0; s0 < TB; s0 += TS) {
+            if (scaled) {
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    renorm(d[r], dp[r], E[r]);
+                    any |= (E[r] < 0);
+                }
+                scaled = wave_any(any);
+            }
+#pragma unroll
+            for (int t = 0; t < TS; ++t) {
+                const int l = lb + s0 + t;
+                const double4 k = cf[buf][s0 + t];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (jj[r] >= 0 && l <= L)
+                        out[(size_t)l * a.nring + jj[r]] = (E[r] == 0) ? d[r] : ldexp(d[r], E[r]);
+                    const double u = fma(x[r], k.x, k.y);
+                    const double dn = fma(-k.z, dp[r], u * d[r]);
+                    dp[r] = d[r];
+                    d[r] = dn;
+                }
+            }
+        }
+        if (tid < TB && kb + 1 < nblk) {
+            double A, nB, F2;
+            recursion_coefs(lb + TB + tid, mb, ms, L, A, nB, F2);
+            cf[buf ^ 1][tid] = make_double4(A, nB, F2, 0.0);
+        }
+        __syncthreads();
+    }
+}
+
+// ================================================================== forward
+// Weights of step l: w1 = conj(b_{l,mb}) s_{l,msky} for the direct ring and
+// w2 = (-1)^(l-msky) conj(b_{l,-mb}) s_{l,msky} for the mirror ring.
+struct RawW {
+    double br, bi, b2r, b2i, sr, si;
+};
+
+__device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int l, int mb, int ms)
+{
+    RawW w{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (l <= a.lmax) {
+        const double2* blm = reinterpret_cast<const double2*>(a.blm);
+        const double2* alm = reinterpret_cast<const double2*>(a.alm);
+        const double2 b1 = blm[(size_t)(mb + a.mbmax) * (a.lmax + 1) + l];
+        const double2 b2 = blm[(size_t)(-mb + a.mbmax) * (a.lmax + 1) + l];
+        const double2 s = alm[packed_index(a.lmax, l, ms)];
+        w = RawW{b1.x, b1.y, b2.x, b2.y, s.x, s.y};
+    }
+    return w;
+}
+
+__device__ __forceinline__ void finish_weights(const RawW& w, int l, int ms, double4& out)
+{
+    // conj(b) * s
+    const double w1r = w.br * w.sr + w.bi * w.si;
+    const double w1i = w.br * w.si - w.bi * w.sr;
+    const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
+    const double w2r = sg * (w.b2r * w.sr + w.b2i * w.si);
+    const double w2i = sg * (w.b2r * w.si - w.b2i * w.sr);
+    out = make_double4(w1r, w1i, w2r, w2i);
+}
+
+template <int R, int NT, bool ACC>
+__device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
+                                          const double (&x)[R], double (&d)[R], double (&dp)[R],
+                                          double (&c1r)[R], double (&c1i)[R], double (&c2r)[R], double (&c2i)[R])
+{
+#pragma unroll
+    for (int t = 0; t < TS; ++t) {
+        const double4 k = cf[s0 + t][0];
+        double4 w;
+        if (ACC) w = cf[s0 + t][1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ACC) {
+                c1r[r] = fma(w.x, d[r], c1r[r]);
+                c1i[r] = fma(w.y, d[r], c1i[r]);
+                c2r[r] = fma(w.z, d[r], c2r[r]);
+                c2i[r] = fma(w.w, d[r], c2i[r]);
+            }
+            const double u = fma(x[r], k.x, k.y);
+            const double dn = fma(-k.z, dp[r], u * d[r]);
+            dp[r] = d[r];
+            d[r] = dn;
+        }
+    }
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
+{
+    __shared__ double4 cf[2][TB][2];   // {A, nB, F2, -}, {w1r, w1i, w2r, w2i}
+    const int tid = threadIdx.x;
+    const int ci = blockIdx.x / a.ntile;
+    const int tile = blockIdx.x - ci * a.ntile;
+    const int mb = a.col.mb[ci], ms = a.col.ms[ci];
+    const int L = a.lmax;
+    const int l0 = max(abs(mb), ms);
+    const SeedShape sh = seed_shape(mb, ms);
+    const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
+
+    double x[R], d[R], dp[R], c1r[R], c1i[R], c2r[R], c2i[R];
+    int E[R], jd[R], jm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int s = tile * (NT * R) + r * NT + tid;
+        jd[r] = -1; jm[r] = -1;
+        x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
+        c1r[r] = 0.0; c1i[r] = 0.0; c2r[r] = 0.0; c2i[r] = 0.0;
+        if (s < a.nslot) {
+            jd[r] = a.slots[2 * s];
+            jm[r] = a.slots[2 * s + 1];
+            const int j = jd[r];
+            x[r] = a.ring.x[j];
+            seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
+        }
+    }
+    bool scaled = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
+    scaled = wave_any(scaled);
+    bool acc_on = (a.skip_exp <= 0);
+
+    if (tid < TB) {
+        const int l = l0 + tid;
+        double A, nB, F2;
+        recursion_coefs(l, mb, ms, L, A, nB, F2);
+        cf[0][tid][0] = make_double4(A, nB, F2, 0.0);
+        finish_weights(load_weights_raw(a, l, mb, ms), l, ms, cf[0][tid][1]);
+    }
+    __syncthreads();
+    const int nblk = (L - l0) / TB + 1;
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int buf = kb & 1;
+        const int lb = l0 + kb * TB;
+        RawW raw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const bool stage = (tid < TB) && (kb + 1 < nblk);
+        if (stage) raw = load_weights_raw(a, lb + TB + tid, mb, ms);   // in flight during the block
+        for (int s0 = 0; s0 < TB; s0 += TS) {
+            if (scaled) {
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = renorm(d[r], dp[r], E[r]);
+                    if (k != 0) {
+                        c1r[r] = ldexp(c1r[r], k); c1i[r] = ldexp(c1i[r], k);
+                        c2r[r] = ldexp(c2r[r], k); c2i[r] = ldexp(c2i[r], k);
+                    }
+                    any |= (E[r] < 0);
+                }
+                scaled = wave_any(any);
+            }
+            if (!acc_on) {
+                bool hot = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) hot |= chain_hot(d[r], dp[r], E[r], a.skip_exp);
+                acc_on = wave_any(hot);
+            }
+            if (acc_on)
+                fwd_steps<R, NT, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+            else
+                fwd_steps<R, NT, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+        }
+        if (stage) {
+            const int l = lb + TB + tid;
+            double A, nB, F2;
+            recursion_coefs(l, mb, ms, L, A, nB, F2);
+            cf[buf ^ 1][tid][0] = make_double4(A, nB, F2, 0.0);
+            finish_weights(raw, l, ms, cf[buf ^ 1][tid][1]);
+        }
+        __syncthreads();
+    }
+
+    double2* C = reinterpret_cast<double2*>(a.C);
+    const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+    const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (jd[r] >= 0) {
+            C[row_d + jd[r]] = make_double2(ldexp(c1r[r], E[r]), ldexp(c1i[r], E[r]));
+            if (jm[r] >= 0)
+                C[row_m + jm[r]] = make_double2(ldexp(c2r[r], E[r]), ldexp(c2i[r], E[r]));
+        }
+    }
+}
+
+// ================================================================== adjoint
+// Per column and l: u_l = sum_j d^l(beta_j) Cbar_j over the direct rings (U)
+// and sum_j d^l(beta_j) Cbar_{-mb,msky}(pi - beta_j) over the mirror rings (V).
+// Each lane sums its R chains in registers; the workgroup then reduces the
+// NT lane sums of TS consecutive l through LDS in a fixed order.
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
+{
+    static_assert(NT % (4 * TR) == 0 && TS % TR == 0, "reduction split");
+    constexpr int G = NT / (4 * TR);   // lanes per reduced value
+    static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "reduction group within a wave");
+    __shared__ double4 cf[2][TB];
+    __shared__ double4 red[TR][NT];
+
+    const int tid = threadIdx.x;
+    const int ci = blockIdx.x / a.ntile;
+    const int tile = blockIdx.x - ci * a.ntile;
+    const int mb = a.col.mb[ci], ms = a.col.ms[ci];
+    const int L = a.lmax;
+    const int l0 = max(abs(mb), ms);
+    const SeedShape sh = seed_shape(mb, ms);
+    const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
+    const double2* Cbar = reinterpret_cast<const double2*>(a.Cbar);
+    const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+    const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+
+    double x[R], d[R], dp[R], g1r[R], g1i[R], g2r[R], g2i[R];
+    int E[R], jd[R], jm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int s = tile * (NT * R) + r * NT + tid;
+        jd[r] = -1; jm[r] = -1;
+        x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
+        g1r[r] = 0.0; g1i[r] = 0.0; g2r[r] = 0.0; g2i[r] = 0.0;
+        if (s < a.nslot) {
+            jd[r] = a.slots[2 * s];
+            jm[r] = a.slots[2 * s + 1];
+            const int j = jd[r];
+            x[r] = a.ring.x[j];
+            seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
+        }
+    }
+    // A scaled chain (E < 0, |d| < 2^-900) contributes nothing; its cotangent is
+    // loaded when it folds into plain doubles.
+    auto load_g = [&](int r) {
+        if (jd[r] >= 0 && E[r] == 0) {
+            const double2 v1 = Cbar[row_d + jd[r]];
+            g1r[r] = v1.x; g1i[r] = v1.y;
+            if (jm[r] >= 0) {
+                const double2 v2 = Cbar[row_m + jm[r]];
+                g2r[r] = v2.x; g2i[r] = v2.y;
+            }
+        }
+    };
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_g(r);
+    bool scaled = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
+    scaled = wave_any(scaled);
+    bool acc_on = (a.skip_exp <= 0);
+
+    double2* U = reinterpret_cast<double2*>(a.U) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
+    double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
+    const size_t urow = packed_index(L, 0, ms);   // + l
+
+    if (tid < TB) {
+        double A, nB, F2;
+        recursion_coefs(l0 + tid, mb, ms, L, A, nB, F2);
+        cf[0][tid] = make_double4(A, nB, F2, 0.0);
+    }
+    __syncthreads();
+    const int nblk = (L - l0) / TB + 1;
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int buf = kb & 1;
+        const int lb = l0 + kb * TB;
+        for (int s0 = 0; s0 < TB; s0 += TS) {
+            if (scaled) {
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool was = E[r] < 0;
+                    renorm(d[r], dp[r], E[r]);
+                    if (was && E[r] == 0) load_g(r);
+                    any |= (E[r] < 0);
+                }
+                scaled = wave_any(any);
+            }
+            if (!acc_on) {
+                bool hot = false;
+#pragma unroll
+                for (int r = 0; r < R; ++r) hot |= chain_hot(d[r], dp[r], E[r], a.skip_exp);
+                acc_on = __syncthreads_or(hot) != 0;      // workgroup-uniform
+            }
+            if (acc_on) {
+                for (int h = 0; h < TS; h += TR) {
+#pragma unroll
+                for (int t = 0; t < TR; ++t) {
+                    const double4 k = cf[buf][s0 + h + t];
+                    double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        p1r = fma(d[r], g1r[r], p1r);
+                        p1i = fma(d[r], g1i[r], p1i);
+                        p2r = fma(d[r], g2r[r], p2r);
+                        p2i = fma(d[r], g2i[r], p2i);
+                        const double u = fma(x[r], k.x, k.y);
+                        const double dn = fma(-k.z, dp[r], u * d[r]);
+                        dp[r] = d[r];
+                        d[r] = dn;
+                    }
+                    red[t][tid] = make_double4(p1r, p1i, p2r, p2i);
+                }
+                __syncthreads();
+                {
+                    const int o = tid / G, sub = tid - o * G;
+                    const int t = o >> 2, comp = o & 3;
+                    double v = 0.0;
+                    for (int n = sub; n < NT; n += G) {
+                        const double4 q = red[t][n];
+                        v += comp == 0 ? q.x : comp == 1 ? q.y : comp == 2 ? q.z : q.w;
+                    }
+#pragma unroll
+                    for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+                    const int l = lb + s0 + h + t;
+                    if (sub == 0 && l <= L) {
+                        double* dst = reinterpret_cast<double*>(comp < 2 ? U : V) + 2 * (urow + l) + (comp & 1);
+                        *dst = v;
+                    }
+                }
+                __syncthreads();
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < TS; ++t) {
+                    const double4 k = cf[buf][s0 + t];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double u = fma(x[r], k.x, k.y);
+                        const double dn = fma(-k.z, dp[r], u * d[r]);
+                        dp[r] = d[r];
+                        d[r] = dn;
+                    }
+                }
+                if (tid < TS) {
+                    const int l = lb + s0 + tid;
+                    if (l <= L) {
+                        U[urow + l] = make_double2(0.0, 0.0);
+                        V[urow + l] = make_double2(0.0, 0.0);
+                    }
+                }
+            }
+        }
+        if (tid < TB && kb + 1 < nblk) {
+            double A, nB, F2;
+            recursion_coefs(lb + TB + tid, mb, ms, L, A, nB, F2);
+            cf[buf ^ 1][tid] = make_double4(A, nB, F2, 0.0);
+        }
+        __syncthreads();
+    }
+}
+
+// u(mb, ms, l) = sum_tiles U[mb] + (-1)^(l-ms) sum_tiles V[-mb], defined for l >= max(|mb|, ms)
+__device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int l, size_t k)
+{
+    const double2* U = reinterpret_cast<const double2*>(e.U);
+    const double2* V = reinterpret_cast<const double2*>(e.V);
+    const size_t stride_t = (size_t)(2 * e.mbmax + 1) * (size_t)e.P;
+    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
+    for (int t = 0; t < e.ntile; ++t) {
+        const double2 a = U[t * stride_t + (size_t)(mb + e.mbmax) * e.P + k];
+        const double2 b = V[t * stride_t + (size_t)(-mb + e.mbmax) * e.P + k];
+        ur += a.x; ui += a.y; vr += b.x; vi += b.y;
+    }
+    const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
+    return make_double2(ur + sg * vr, ui + sg * vi);
+}
+
+// alm_bar_{l,ms} = sum_mb b_{l,mb} u(mb, ms, l)
+__global__ void __launch_bounds__(256) k_adj_sky(const EpiArgs e)
+{
+    const int ms = blockIdx.y;
+    const int l = ms + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > e.lmax) return;
+    const size_t k = packed_index(e.lmax, l, ms);
+    const double2* blm = reinterpret_cast<const double2*>(e.blm);
+    double ar = 0.0, ai = 0.0;
+    for (int mb = -e.mbmax; mb <= e.mbmax; ++mb) {
+        if (l < abs(mb)) continue;
+        const double2 u = u_value(e, mb, ms, l, k);
+        const double2 b = blm[(size_t)(mb + e.mbmax) * (e.lmax + 1) + l];
+        ar += b.x * u.x - b.y * u.y;
+        ai += b.x * u.y + b.y * u.x;
+    }
+    reinterpret_cast<double2*>(e.alm_bar)[k] = make_double2(ar, ai);
+}
+
+// blm_bar_{l,mb} = sum_{ms <= l} s_{l,ms} conj(u(mb, ms, l))
+__global__ void __launch_bounds__(256) k_adj_beam(const EpiArgs e)
+{
+    const int mb = (int)blockIdx.y - e.mbmax;
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > e.lmax) return;
+    double2* out = reinterpret_cast<double2*>(e.blm_bar) + (size_t)(mb + e.mbmax) * (e.lmax + 1) + l;
+    if (l < abs(mb)) {
+        *out = make_double2(0.0, 0.0);
+        return;
+    }
+    const double2* alm = reinterpret_cast<const double2*>(e.alm);
+    double br = 0.0, bi = 0.0;
+#pragma unroll 4
+    for (int ms = 0; ms <= l; ++ms) {
+        const size_t k = packed_index(e.lmax, l, ms);
+        const double2 u = u_value(e, mb, ms, l, k);
+        const double2 s = alm[k];
+        br += s.x * u.x + s.y * u.y;
+        bi += s.y * u.x - s.x * u.y;
+    }
+    *out = make_double2(br, bi);
+}
+
+template <typename Args>
+int launch_grid(void (*kern)(Args), const Args& a, int blocks, int nt, void* stream)
+{
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(nt), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+bool tile_supported(int op, Tile t)
+{
+    if (t.NT != 256) return false;
+    if (op == 0) return t.R == 1 || t.R == 4;
+    return t.R == 2 || t.R == 4 || t.R == 8;
+}
+
+int launch_wigner(const WignerArgs& a, Tile t, void* stream)
+{
+    const int blocks = a.npair * a.ntile;
+    switch (t.R) {
+    case 1: return launch_grid(k_wigner<1, 256>, a, blocks, 256, stream);
+    case 4: return launch_grid(k_wigner<4, 256>, a, blocks, 256, stream);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_fwd(const FwdArgs& a, Tile t, void* stream)
+{
+    const int blocks = a.ncol * a.ntile;
+    switch (t.R) {
+    case 2: return launch_grid(k_fwd<2, 256>, a, blocks, 256, stream);
+    case 4: return launch_grid(k_fwd<4, 256>, a, blocks, 256, stream);
+    case 8: return launch_grid(k_fwd<8, 256>, a, blocks, 256, stream);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_adj(const AdjArgs& a, Tile t, void* stream)
+{
+    const int blocks = a.ncol * a.ntile;
+    switch (t.R) {
+    case 2: return launch_grid(k_adj<2, 256>, a, blocks, 256, stream);
+    case 4: return launch_grid(k_adj<4, 256>, a, blocks, 256, stream);
+    case 8: return launch_grid(k_adj<8, 256>, a, blocks, 256, stream);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_adj_epilogue(const EpiArgs& e, void* stream)
+{
+    const int nt = 256;
+    if (e.alm_bar) {
+        dim3 grid((e.lmax + 1 + nt - 1) / nt, e.lmax + 1);
+        hipLaunchKernelGGL(k_adj_sky, grid, dim3(nt), 0, (hipStream_t)stream, e);
+        const int rc = (int)hipGetLastError();
+        if (rc) return rc;
+    }
+    if (e.blm_bar) {
+        dim3 grid((e.lmax + 1 + nt - 1) / nt, 2 * e.mbmax + 1);
+        hipLaunchKernelGGL(k_adj_beam, grid, dim3(nt), 0, (hipStream_t)stream, e);
+        const int rc = (int)hipGetLastError();
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+}  // namespace tc

@@ -1,0 +1,327 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Gates (readings of the paper's silence on error metrics):
+* d (wigner_d_rings): absolute error, |d| <= 1: <= 1e-10 for lmax <= 4096, 3e-10 up to 8192.
+* C: per column (mb, msky), max_j |dC| / max_j |C_oracle| <= 1e-11; an all-zero oracle
+  column must come out exactly zero.
+* gradients: normwise over the whole sky gradient, per mb row for the beam gradient, <= 1e-11.
+Inputs are seeded synthetic rings, skies and beams (paper_1002_1050_amd.synthetic).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1002_1050_amd import synthetic as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GATE_C = 1e-11
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1002_1050_amd import _binding
+    _binding.lib()
+    return _binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def column_gate(got, ref):
+    """max over columns of max_j|got - ref| / max_j|ref|; zero columns must match exactly."""
+    got = got.reshape(-1, got.shape[-1])
+    ref = ref.reshape(-1, ref.shape[-1])
+    num = np.abs(got - ref).max(axis=1)
+    den = np.abs(ref).max(axis=1)
+    zero = den == 0
+    assert np.all(num[zero] == 0), "non-zero result in an all-zero column"
+    return float((num[~zero] / den[~zero]).max()) if np.any(~zero) else 0.0
+
+
+# ----------------------------------------------------------------- wigner_d_rings
+
+def test_wigner_small_all_cases(B, orc):
+    L = 64
+    x = np.concatenate([S.ring_cosines(129), [1.0, -1.0, 0.0, 0.5, -0.999999]])
+    pairs = [(0, 0), (0, 1), (1, 0), (3, 1), (-3, 1), (2, 5), (-2, 5), (4, -6), (-7, 3), (7, 3),
+             (5, 5), (-5, 5), (5, -5), (0, -4), (-6, -6), (64, 64), (-64, 3), (64, -64), (10, 64), (-13, -40)]
+    mb = [p[0] for p in pairs]
+    ms = [p[1] for p in pairs]
+    say(f"wigner_d_rings L={L} npair={len(pairs)} nring={x.size}")
+    got = B.wigner_d_rings(L, mb, ms, x).cpu().numpy()
+    ref = orc.wigner_d(L, mb, ms, x)
+    err = np.abs(got - ref).max()
+    say(f"  max abs err {err:.3e}")
+    assert err <= 1e-13
+
+
+def test_wigner_large_l_sampled_rings(B, orc):
+    L = 4096
+    xa = S.ring_cosines(2 * L)
+    rings = np.unique(np.concatenate([np.arange(0, 40), np.arange(40, 2 * L, 97), 2 * L - 1 - np.arange(0, 40)]))
+    x = xa[rings]
+    pairs = [(0, 0), (14, 14), (-14, 300), (3, 1000), (14, 3000), (0, 4000), (-9, 5), (7, -2), (-12, -2048), (16, 4096)]
+    mb = [p[0] for p in pairs]
+    ms = [p[1] for p in pairs]
+    say(f"wigner_d_rings L={L} npair={len(pairs)} nring={x.size}")
+    got = B.wigner_d_rings(L, mb, ms, x).cpu().numpy()
+    ref = orc.wigner_d(L, mb, ms, x)
+    err = np.abs(got - ref).max()
+    say(f"  max abs err {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_wigner_tiny_values_relative(B, orc):
+    """Values far below 2^-900 at the seed that grow into the double range keep full relative
+    precision (the scaled phase is exact up to rounding)."""
+    L = 2000
+    # rings whose seeds lie near 2^-1000 .. 2^-1150 and whose chains reach |d| ~ 2^-4 .. 2^-50
+    x = S.ring_cosines(4000)[[500, 550, 600, 620, 650, 700, 3300, 3350, 3400, 3450, 3500]]
+    pairs = [(3, 800), (0, 1000), (-3, 800), (2, 1000)]
+    say(f"wigner_d_rings tiny seeds L={L}")
+    got = B.wigner_d_rings(L, [p[0] for p in pairs], [p[1] for p in pairs], x).cpu().numpy()
+    ref = orc.wigner_d(L, [p[0] for p in pairs], [p[1] for p in pairs], x)
+    mant, ex = orc.wigner_d(L, [p[0] for p in pairs], [p[1] for p in pairs], x, split=True)
+    l0 = np.array([max(abs(a), abs(b)) for a, b in pairs])
+    assert np.sum(ex[np.arange(len(pairs)), l0, :] < -900) >= 20     # seeds below 2^-900
+    sel = (np.abs(ref) > 1e-250) & (np.abs(ref) < 1e-20)
+    assert sel.sum() > 1000
+    rel = np.abs(got[sel] - ref[sel]) / np.abs(ref[sel])
+    say(f"  {sel.sum()} tiny values, max rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-12
+
+
+# ------------------------------------------------------------------------ forward
+
+def run_fwd(B, L, M, x, alm, blm):
+    return B.totalconv_fwd(L, M, x, dev(alm), dev(blm))
+
+
+def test_fwd_small_workload_full(B, orc):
+    w = S.WORKLOADS["small"]
+    x, alm, blm = w.xring(), w.alm(), w.blm()
+    say(f"totalconv_fwd small L={w.lmax} M={w.mbmax} nring={w.nring}")
+    got = run_fwd(B, w.lmax, w.mbmax, x, alm, blm).cpu().numpy()
+    ref = orc.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm)
+    g = column_gate(got, ref)
+    say(f"  column gate {g:.3e}")
+    assert g <= GATE_C
+
+
+@pytest.mark.parametrize("L,M,nring,seed", [(40, 3, 81, 1), (130, 6, 517, 2), (200, 2, 4500, 3), (33, 0, 64, 4)])
+def test_fwd_random_complex_full(B, orc, L, M, nring, seed):
+    """Complex beams and skies without symmetry, odd and even ring counts, several ring tiles."""
+    x = S.ring_cosines(nring)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    alm = rng.standard_normal(S.alm_size(L)) + 1j * rng.standard_normal(S.alm_size(L))
+    alm[: L + 1] = alm[: L + 1].real
+    blm = S.random_beam(L, M, seed + 100)
+    say(f"totalconv_fwd random L={L} M={M} nring={nring}")
+    got = run_fwd(B, L, M, x, alm, blm).cpu().numpy()
+    ref = orc.totalconv_fwd(L, M, x, alm, blm)
+    g = column_gate(got, ref)
+    say(f"  column gate {g:.3e}")
+    assert g <= GATE_C
+
+
+def test_fwd_unpaired_and_pole_rings(B, orc):
+    """A ring set with no mirror pairs, the poles and the equator (single-ring path, -inf rule)."""
+    L, M = 50, 4
+    x = np.array([1.0, 0.93, 0.4, 0.0, -0.21, -0.77, -1.0, 0.999999999])
+    alm = S.sky_alm(L, 9)
+    blm = S.random_beam(L, M, 10)
+    say(f"totalconv_fwd unpaired rings L={L} M={M} nring={x.size}")
+    got = run_fwd(B, L, M, x, alm, blm).cpu().numpy()
+    ref = orc.totalconv_fwd(L, M, x, alm, blm)
+    g = column_gate(got, ref)
+    say(f"  column gate {g:.3e}")
+    assert g <= GATE_C
+
+
+def test_fwd_degenerate_sizes(B, orc):
+    for (L, M, x) in [(0, 0, np.array([0.3])), (1, 1, np.array([0.5, -0.5])), (5, 0, np.array([0.0])),
+                      (7, 7, S.ring_cosines(3))]:
+        alm = S.sky_alm(L, 3)
+        blm = S.random_beam(L, M, 4)
+        say(f"totalconv_fwd degenerate L={L} M={M} nring={x.size}")
+        got = run_fwd(B, L, M, x, alm, blm).cpu().numpy()
+        ref = orc.totalconv_fwd(L, M, x, alm, blm)
+        assert column_gate(got, ref) <= GATE_C
+
+
+def _sample_columns(L, M, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mb = rng.integers(-M, M + 1, n)
+    ms = np.concatenate([[0, L, L - 1, 1], (rng.random(n - 4) ** 0.7 * (L + 1)).astype(int)])
+    ms = np.minimum(ms, L)
+    mb[:4] = [0, M, -M, 1]
+    return mb.astype(np.int32), ms.astype(np.int32)
+
+
+@pytest.mark.parametrize("name,ncol", [("medium", 40), ("lmax4096", 16)])
+def test_fwd_full_size_sampled_columns(B, orc, name, ncol):
+    """Full-size launch (the benchmark's configuration); the oracle evaluates sampled columns
+    over every ring."""
+    w = S.WORKLOADS[name]
+    x, alm, blm = w.xring(), w.alm(), w.blm()
+    say(f"totalconv_fwd {name} L={w.lmax} M={w.mbmax} nring={w.nring}")
+    C = run_fwd(B, w.lmax, w.mbmax, x, alm, blm)
+    mb, ms = _sample_columns(w.lmax, w.mbmax, ncol, 11)
+    idx = torch.from_numpy(((mb + w.mbmax) * (w.lmax + 1) + ms).astype(np.int64)).to("cuda")
+    got = C.reshape(-1, w.nring).index_select(0, idx).cpu().numpy()
+    del C
+    torch.cuda.empty_cache()
+    ref = orc.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, cols=(mb, ms))
+    g = column_gate(got, ref)
+    say(f"  column gate {g:.3e} over {ncol} columns")
+    assert g <= GATE_C
+
+
+def test_fwd_deterministic(B):
+    w = S.WORKLOADS["small"]
+    x, alm, blm = w.xring(), dev(w.alm()), dev(w.blm())
+    say("totalconv_fwd determinism")
+    a = B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm).cpu()
+    b = B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm).cpu()
+    assert torch.equal(a, b)
+
+
+def test_fwd_rejects_bad_input(B):
+    x = S.ring_cosines(8)
+    alm = dev(S.sky_alm(4, 1))
+    blm = dev(S.random_beam(4, 1, 1))
+    bad = x.copy()
+    bad[2] = 2.0
+    with pytest.raises(B.TotalConvError, match="cosbeta"):
+        B.totalconv_fwd(4, 1, bad, alm, blm)
+    with pytest.raises(ValueError):
+        B.totalconv_fwd(4, 2, x, alm, blm)
+
+
+# ------------------------------------------------------------------------ adjoint
+
+def rel_norm(got, ref):
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+@pytest.mark.parametrize("L,M,nring", [(40, 4, 81), (90, 6, 300), (64, 0, 64)])
+def test_adj_vs_oracle_full(B, orc, L, M, nring):
+    x = S.ring_cosines(nring)
+    alm = S.sky_alm(L, 21) + 0.0j
+    blm = S.random_beam(L, M, 22)
+    G = S.random_cbar(L, M, nring, 23)
+    say(f"totalconv_adj L={L} M={M} nring={nring}")
+    ga, gb = B.totalconv_adj(L, M, x, dev(alm), dev(blm), dev(G))
+    ra, rb = orc.totalconv_adj(L, M, x, alm, blm, G)
+    ea = rel_norm(ga.cpu().numpy(), ra)
+    gbn = gb.cpu().numpy()
+    eb = max(rel_norm(gbn[r], rb[r]) for r in range(2 * M + 1) if np.any(rb[r] != 0))
+    say(f"  sky grad {ea:.3e}  beam grad {eb:.3e}")
+    assert ea <= GATE_C and eb <= GATE_C
+    for r in range(2 * M + 1):
+        assert np.all(gbn[r, : abs(r - M)] == 0)
+
+
+def test_adj_dot_product_medium(B):
+    """<G, A s> = <A^H G, s> at a size the oracle cannot do in full."""
+    L, M, nring = 700, 9, 1400
+    x = S.ring_cosines(nring)
+    alm = dev(S.sky_alm(L, 31) + 0.0j)
+    blm = dev(S.random_beam(L, M, 32))
+    G = dev(S.random_cbar(L, M, nring, 33))
+    say(f"dot product L={L} M={M} nring={nring}")
+    C = B.totalconv_fwd(L, M, x, alm, blm)
+    ga, gb = B.totalconv_adj(L, M, x, alm, blm, G)
+    lhs = torch.vdot(G.flatten(), C.flatten()).item()
+    rhs_a = torch.vdot(ga.flatten(), alm.flatten()).item()
+    rhs_b = torch.sum(torch.conj(blm) * gb).item()
+    say(f"  <G,C>={lhs:.6e}  <ga,a>={rhs_a:.6e}  <b,gb>={rhs_b:.6e}")
+    assert abs(lhs - rhs_a) <= 1e-12 * abs(lhs)
+    assert abs(lhs - rhs_b) <= 1e-12 * abs(lhs)
+
+
+def test_adj_large_sampled_sky_gradient(B, orc):
+    """lmax 2048 forward + adjoint with loss 0.5||C - C_target||^2; the oracle evaluates the sky
+    gradient for sampled msky (every mb and ring of those columns)."""
+    w = S.WORKLOADS["adjoint"]
+    x, alm, blm = w.xring(), w.alm(), w.blm()
+    target = S.sky_alm(w.lmax, w.target_seed)
+    say(f"adjoint workload L={w.lmax} M={w.mbmax} nring={w.nring}")
+    a_d, b_d = dev(alm), dev(blm)
+    C = B.totalconv_fwd(w.lmax, w.mbmax, x, a_d, b_d)
+    T = B.totalconv_fwd(w.lmax, w.mbmax, x, dev(target), b_d)
+    G = C - T
+    del C, T
+    ga, gb = B.totalconv_adj(w.lmax, w.mbmax, x, a_d, b_d, G)
+    ga = ga.cpu().numpy()
+    msel = [0, 7, 1500, 2048]
+    nb = 2 * w.mbmax + 1
+    cols_mb = np.repeat(np.arange(-w.mbmax, w.mbmax + 1), len(msel)).astype(np.int32)
+    cols_ms = np.tile(np.array(msel), nb).astype(np.int32)
+    idx = torch.from_numpy(((cols_mb + w.mbmax) * (w.lmax + 1) + cols_ms).astype(np.int64)).to("cuda")
+    Gs = G.reshape(-1, w.nring).index_select(0, idx).cpu().numpy()
+    del G
+    torch.cuda.empty_cache()
+    u = orc.column_sums(w.lmax, w.mbmax, x, Gs, (cols_mb, cols_ms))
+    u = u[..., 0].astype(np.float64) + 1j * u[..., 1].astype(np.float64)
+    u = u.reshape(nb, len(msel), w.lmax + 1)
+    worst = 0.0
+    for k, m in enumerate(msel):
+        ref = (blm[:, m:] * u[:, k, m:]).sum(axis=0)
+        start = S.alm_index(w.lmax, m, m)
+        got = ga[start:start + w.lmax + 1 - m]
+        worst = max(worst, rel_norm(got, ref))
+    say(f"  sampled sky-gradient rows: worst rel {worst:.3e}")
+    assert worst <= GATE_C
+
+
+# ------------------------------------------------------------------------ autograd
+
+def test_autograd_central_differences(B):
+    from paper_1002_1050_amd import TotalConv
+    L, M, nring = 24, 3, 49
+    x = S.ring_cosines(nring)
+    alm = dev(S.sky_alm(L, 41) + 0.0j).requires_grad_(True)
+    blm = dev(S.random_beam(L, M, 42)).requires_grad_(True)
+    T = dev(S.random_cbar(L, M, nring, 43))
+    say("autograd central differences")
+
+    def loss(a, b):
+        C = TotalConv.apply(a, b, x, L, M)
+        return 0.5 * torch.sum(torch.abs(C - T) ** 2)
+
+    out = loss(alm, blm)
+    out.backward()
+    ga, gb = alm.grad.clone(), blm.grad.clone()
+    gmax = max(ga.abs().max().item(), gb.abs().max().item())
+    rng = np.random.Generator(np.random.PCG64(7))
+    h = 1e-3
+    with torch.no_grad():
+        for k in rng.choice(alm.numel(), 16, replace=False):
+            for unit in (1.0, 1j):
+                d = torch.zeros_like(alm)
+                d[k] = h * unit
+                fd = ((loss(alm + d, blm) - loss(alm - d, blm)) / (2 * h)).item()
+                g = ga[k].real.item() if unit == 1.0 else ga[k].imag.item()
+                assert abs(fd - g) <= 1e-8 * gmax
+        for _ in range(16):
+            r, l = int(rng.integers(0, 2 * M + 1)), int(rng.integers(abs(0), L + 1))
+            if l < abs(r - M):
+                continue
+            for unit in (1.0, 1j):
+                d = torch.zeros_like(blm)
+                d[r, l] = h * unit
+                fd = ((loss(alm, blm + d) - loss(alm, blm - d)) / (2 * h)).item()
+                g = gb[r, l].real.item() if unit == 1.0 else gb[r, l].imag.item()
+                assert abs(fd - g) <= 1e-8 * gmax
