@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="wall-clock budget of the oracle sample (0 disables)")
     p.add_argument("--fwd-only", action="store_true", help="time the forward alone")
+    p.add_argument("--batched-reps", type=int, default=3,
+                   help="interleaved repetitions of the sixteen-detector batched-vs-plain comparison (0 skips)")
+    p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     return p.parse_args()
 
 
@@ -79,6 +82,88 @@ def cpu_baseline(w, x, alm, blm, G_cols_fn, seconds):
         "sample": f"{ncols} seeded random (mb, msky) columns x all {w.nring} rings of the {w.name} "
                   f"workload, forward + adjoint column sums, x87 long double, {elapsed:.1f} s",
     }
+
+
+def truncate_sky(S, alm, lmax_sky, lmax):
+    out = np.zeros(S.alm_size(lmax), np.complex128)
+    for m in range(lmax + 1):
+        out[S.alm_index(lmax, m, m):S.alm_index(lmax, lmax, m) + 1] = \
+            alm[S.alm_index(lmax_sky, m, m):S.alm_index(lmax_sky, lmax, m) + 1]
+    return out
+
+
+def batched_compare(reps, tune):
+    """Sixteen detectors (lmax 512..4096 x mbmax 4..14, 2 lmax rings each, one sky at lmax 4096):
+    sixteen plain totalconv_fwd calls on one stream (each with its own tile) against one
+    tc_plan_execute of the persistent, graph-captured plan.  Interleaved repetitions."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import autotune
+    from paper_1002_1050_amd import synthetic as S
+    w = S.WORKLOADS["batched16"]
+    dev = torch.device("cuda:0")
+    alm_h = S.sky_alm(w.lmax, w.sky_seed)
+    alm = torch.from_numpy(alm_h).to(dev)
+    dets, plain = [], []
+    for d in w.detectors:
+        x = d.xring()
+        blm = torch.from_numpy(d.blm()).to(dev)
+        C = torch.empty((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128, device=dev)
+        a_d = torch.from_numpy(truncate_sky(S, alm_h, w.lmax, d.lmax)).to(dev)
+        R = autotune.tune_plain(B.TC_OP_FWD, d.lmax, d.mbmax, x, a_d, blm, reps=1) if tune else 0
+        dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": x, "blm": blm, "C": C})
+        plain.append((d, x, a_d, blm, C, R))
+        log(f"  detector lmax={d.lmax} mbmax={d.mbmax} nring={d.nring} plain R={R or 'default'}")
+
+    def run_plain():
+        for d, x, a_d, blm, C, R in plain:
+            B.set_tile(B.TC_OP_FWD, R)
+            B.totalconv_fwd(d.lmax, d.mbmax, x, a_d, blm, out=C)
+        B.set_tile(B.TC_OP_FWD, 0)
+
+    if tune:
+        Rp, tms = autotune.tune_plan(B.TC_OP_FWD, lambda: B.Plan(B.TC_OP_FWD, dets, w.lmax, alm), reps=1,
+                                     key_extra="batched16")
+        log(f"  plan tile R={Rp} (trial ms {tms})")
+        B.set_tile(B.TC_OP_FWD, Rp)
+    plan = B.Plan(B.TC_OP_FWD, dets, w.lmax, alm)
+    B.set_tile(B.TC_OP_FWD, 0)
+    s = torch.cuda.current_stream(dev)
+    run_plain()
+    plan.execute()
+    torch.cuda.synchronize()
+    tp, tb = [], []
+    for i in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(s)
+        run_plain()
+        e[1].record(s)
+        torch.cuda.synchronize()
+        e[2].record(s)
+        plan.execute()
+        e[3].record(s)
+        torch.cuda.synchronize()
+        tp.append(e[0].elapsed_time(e[1]))
+        tb.append(e[2].elapsed_time(e[3]))
+        log(f"  rep {i + 1}/{reps}: plain {tp[-1]:.1f} ms, batched {tb[-1]:.1f} ms")
+    ratios = [a / b for a, b in zip(tp, tb)]
+    terms = w.terms()
+    res = {
+        "workload": "sixteen detectors, lmax {512,1024,2048,4096} x mbmax {4,6,9,14}, 2 lmax rings each, "
+                    "one sky at lmax 4096, forward",
+        "terms": terms,
+        "plain_ms_median": float(np.median(tp)),
+        "batched_ms_median": float(np.median(tb)),
+        "plain_terms_per_s": terms / (np.median(tp) * 1e-3),
+        "batched_terms_per_s": terms / (np.median(tb) * 1e-3),
+        "speedup_median": float(np.median(ratios)),
+        "speedup_min": float(np.min(ratios)),
+        "speedup_max": float(np.max(ratios)),
+        "plan_tile_R": plan.tile,
+        "reps": reps,
+    }
+    plan.close()
+    return res
 
 
 def main():
@@ -195,6 +280,12 @@ def main():
 
         log(f"cpu baseline: oracle on a sample, about {args.cpu_seconds:.0f} s")
         result["cpu_baseline"] = cpu_baseline(w, x, alm_h, blm_h, g_cols, args.cpu_seconds)
+        del Gc
+    if args.batched_reps > 0:
+        del C, G
+        torch.cuda.empty_cache()
+        log("batched sixteen-detector comparison")
+        result["batched"] = batched_compare(args.batched_reps, not args.no_tune)
     print(json.dumps(result), flush=True)
 
 

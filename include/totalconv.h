@@ -129,6 +129,58 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
                   double* alm_bar, double* blm_bar,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Tile selection for later calls in this process (not in the paper; a tuning
+ * knob of this implementation).  Each lane walks R chains; a workgroup covers
+ * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8})
+ * or TC_OP_WIGNER (R in {1, 4}); R = 0 restores the built-in choice.  Affects
+ * the workspace sizes reported afterwards.  Returns TC_EINVAL for other values.
+ * Not synchronised: set it from the thread that issues the calls.
+ */
+int tc_set_tile(int op, int R);
+
+/* The R that the next call of `op` at this lmax would use. */
+int tc_get_tile(int op, int lmax);
+
+/*
+ * Batched plan: many detectors -- each with its own beam, mbmax, lmax and ring
+ * set -- convolved with one shared sky in a single persistent launch that takes
+ * (detector, column, ring tile) items from a queue ordered longest first, all
+ * captured in one HIP graph (the batching is not in the paper; every item
+ * computes the same sum as totalconv_fwd / totalconv_adj).
+ */
+typedef struct tc_detector {
+    int lmax;                /* 0 <= mbmax <= lmax <= lmax_sky                     */
+    int mbmax;
+    int nring;
+    const double* cosbeta;   /* (host) nring ring cosines, copied at plan creation  */
+    const double* blm;       /* beam [2*mbmax+1][lmax+1] complex                    */
+    double* C;               /* forward: out [2*mbmax+1][lmax+1][nring] complex     */
+    const double* Cbar;      /* adjoint: in, layout of C                            */
+    double* blm_bar;         /* adjoint: out, layout of blm, may be NULL            */
+} tc_detector;
+
+/*
+ * Build a plan for op = TC_OP_FWD or TC_OP_ADJ over ndet >= 1 detectors and the
+ * sky alm (packed at lmax_sky).  For the adjoint, alm_bar (layout of alm, may
+ * be NULL) receives the sky gradient summed over all detectors.  The plan keeps
+ * the device pointers it is given (they must stay valid while it is used) and
+ * owns its tables and partial-sum buffers (device memory allocated here and
+ * released by tc_plan_destroy).  Creation is synchronous on `stream`.
+ */
+int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int lmax_sky,
+                   const double* alm, double* alm_bar, void* stream);
+
+/* Enqueue the plan's graph on `stream` (asynchronous). */
+int tc_plan_execute(void* plan, void* stream);
+
+/* Device bytes the plan owns, and the R of its persistent kernel. */
+size_t tc_plan_device_bytes(void* plan);
+int tc_plan_tile(void* plan);
+
+/* Release the plan (synchronises with its last launch first).  NULL is ignored. */
+int tc_plan_destroy(void* plan);
+
 #ifdef __cplusplus
 }
 #endif

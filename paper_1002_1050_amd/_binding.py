@@ -24,6 +24,13 @@ _lib = None
 _lock = threading.Lock()
 
 
+class TcDetector(ctypes.Structure):
+    """struct tc_detector of include/totalconv.h."""
+    _fields_ = [("lmax", ctypes.c_int), ("mbmax", ctypes.c_int), ("nring", ctypes.c_int),
+                ("cosbeta", ctypes.c_void_p), ("blm", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("Cbar", ctypes.c_void_p), ("blm_bar", ctypes.c_void_p)]
+
+
 class TotalConvError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed ({code}): {msg}")
@@ -55,6 +62,20 @@ def lib():
             L.totalconv_fwd.argtypes = [I, I, I, P, P, P, P, P, S, P]
             L.totalconv_adj.restype = I
             L.totalconv_adj.argtypes = [I, I, I, P, P, P, P, P, P, P, S, P]
+            L.tc_set_tile.restype = I
+            L.tc_set_tile.argtypes = [I, I]
+            L.tc_get_tile.restype = I
+            L.tc_get_tile.argtypes = [I, I]
+            L.tc_plan_create.restype = I
+            L.tc_plan_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.POINTER(TcDetector), I, P, P, P]
+            L.tc_plan_execute.restype = I
+            L.tc_plan_execute.argtypes = [P, P]
+            L.tc_plan_destroy.restype = I
+            L.tc_plan_destroy.argtypes = [P]
+            L.tc_plan_device_bytes.restype = S
+            L.tc_plan_device_bytes.argtypes = [P]
+            L.tc_plan_tile.restype = I
+            L.tc_plan_tile.argtypes = [P]
             _lib = L
     return _lib
 
@@ -184,3 +205,67 @@ def totalconv_adj(lmax: int, mbmax: int, cosbeta, alm, blm, Cbar, want_alm=True,
                              _dptr(alm_bar), _dptr(blm_bar), _dptr(ws), ws.numel(), stream)
     _check("totalconv_adj", rc)
     return alm_bar, blm_bar
+
+
+def set_tile(op: int, R: int):
+    """Chains per lane (R) for later calls of `op` in this process; 0 restores the default."""
+    _check("tc_set_tile", lib().tc_set_tile(op, R))
+
+
+def get_tile(op: int, lmax: int) -> int:
+    return int(lib().tc_get_tile(op, lmax))
+
+
+class Plan:
+    """A batched plan (tc_plan_create): many detectors, one shared sky, one graph launch.
+
+    detectors: list of dicts with keys lmax, mbmax, cosbeta (host array), blm (device
+    complex128), and C (forward output) or Cbar / blm_bar (adjoint input / output)."""
+
+    def __init__(self, op: int, detectors, lmax_sky: int, alm, alm_bar=None):
+        import torch
+        self._keep = []
+        arr = (TcDetector * len(detectors))()
+        for i, d in enumerate(detectors):
+            x = _host(d["cosbeta"], np.float64)
+            self._keep.append(x)
+            arr[i].lmax = d["lmax"]
+            arr[i].mbmax = d["mbmax"]
+            arr[i].nring = x.size
+            arr[i].cosbeta = _hptr(x).value
+            arr[i].blm = d["blm"].data_ptr()
+            arr[i].C = d["C"].data_ptr() if d.get("C") is not None else None
+            arr[i].Cbar = d["Cbar"].data_ptr() if d.get("Cbar") is not None else None
+            arr[i].blm_bar = d["blm_bar"].data_ptr() if d.get("blm_bar") is not None else None
+        self._dets = detectors
+        self._alm, self._alm_bar = alm, alm_bar
+        self.device = alm.device
+        handle = ctypes.c_void_p()
+        stream = _stream_handle(torch, self.device)
+        rc = lib().tc_plan_create(ctypes.byref(handle), op, len(detectors), arr, lmax_sky,
+                                  _dptr(alm), _dptr(alm_bar), stream)
+        _check("tc_plan_create", rc)
+        self._h = handle
+
+    @property
+    def tile(self) -> int:
+        return int(lib().tc_plan_tile(self._h))
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().tc_plan_device_bytes(self._h))
+
+    def execute(self):
+        import torch
+        _check("tc_plan_execute", lib().tc_plan_execute(self._h, _stream_handle(torch, self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+"""Tile autotuner: picks R (chains per lane) for plain calls and batched plans.
+
+Each candidate runs the real launch (after one untimed warm-up) and is timed with
+HIP events on the stream it runs on; the fastest wins.  Results are cached in a
+JSON file (``$TC_TUNE_CACHE``, else ``~/.cache/paper_1002_1050_amd/tiles.json``)
+keyed by the operation, sizes and GPU name, so a later process reuses them.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import _binding as B
+
+CANDIDATES = {B.TC_OP_FWD: (2, 4, 8), B.TC_OP_ADJ: (2, 4, 8)}
+
+
+def _cache_path():
+    return os.environ.get("TC_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_1002_1050_amd", "tiles.json")
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time(fn, reps=2):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _gpu_name():
+    import torch
+    return torch.cuda.get_device_name(0).replace(" ", "_")
+
+
+def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=True):
+    """Best R for a plain totalconv_fwd / totalconv_adj call of this shape."""
+    key = f"plain:{op}:{lmax}:{mbmax}:{len(cosbeta)}:{_gpu_name()}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]["R"]
+    times = {}
+    old = B.get_tile(op, lmax)
+    try:
+        for R in CANDIDATES[op]:
+            B.set_tile(op, R)
+            if op == B.TC_OP_FWD:
+                times[R] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
+            else:
+                times[R] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
+    finally:
+        B.set_tile(op, 0)
+    best = min(times, key=times.get)
+    cache = _load()
+    cache[key] = {"R": best, "ms": {str(k): v for k, v in times.items()}, "default_R": old}
+    _store(cache)
+    return best
+
+
+def tune_plan(op, make_plan, reps=2, use_cache=True, key_extra=""):
+    """Best R for a batched plan; make_plan() builds the plan for the current tile setting."""
+    key = f"plan:{op}:{key_extra}:{_gpu_name()}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]["R"], cache[key]["ms"]
+    times = {}
+    try:
+        for R in CANDIDATES[op]:
+            B.set_tile(op, R)
+            plan = make_plan()
+            times[R] = _time(plan.execute, reps)
+            plan.close()
+    finally:
+        B.set_tile(op, 0)
+    best = min(times, key=times.get)
+    cache = _load()
+    cache[key] = {"R": best, "ms": {str(k): v for k, v in times.items()}}
+    _store(cache)
+    return best, cache[key]["ms"]

@@ -58,17 +58,12 @@ void split_dd(ld v, double& hi, double& lo)
 
 // ---------------------------------------------------------------- tile choice
 
+int g_tile_override[3] = {0, 0, 0};   // tc_set_tile
+
 tc::Tile default_tile(int op, int lmax)
 {
-    const char* env = nullptr;
-    if (op == TC_OP_WIGNER) env = std::getenv("TC_TILE_WIGNER_R");
-    if (op == TC_OP_FWD) env = std::getenv("TC_TILE_FWD_R");
-    if (op == TC_OP_ADJ) env = std::getenv("TC_TILE_ADJ_R");
     tc::Tile t{op == TC_OP_WIGNER ? 4 : (lmax >= 256 ? 8 : 2), 256};
-    if (env && *env) {
-        tc::Tile e{std::atoi(env), 256};
-        if (tc::tile_supported(op, e)) t = e;
-    }
+    if (op >= 0 && op < 3 && g_tile_override[op] > 0) t.R = g_tile_override[op];
     return t;
 }
 
@@ -254,6 +249,21 @@ extern "C" {
 
 const char* tc_last_error(void) { return g_error.c_str(); }
 
+int tc_set_tile(int op, int R)
+{
+    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
+    if (R != 0 && !tc::tile_supported(op, tc::Tile{R, 256}))
+        return fail(TC_EINVAL, "tc_set_tile: R = %d is not built for op %d", R, op);
+    g_tile_override[op] = R;
+    return TC_OK;
+}
+
+int tc_get_tile(int op, int lmax)
+{
+    if (op < 0 || op > 2) return 0;
+    return default_tile(op, lmax).R;
+}
+
 int tc_abi_version(void) { return 1; }
 
 size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring)
@@ -326,6 +336,7 @@ int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta, const d
     if ((rc = upload(workspace, img, stream))) return rc;
     tc::FwdArgs a{};
     a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
+    a.sky_lmax = lmax;
     a.skip_exp = 100;
     a.ring = ring_ptrs(workspace, L, nring);
     a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
@@ -368,10 +379,253 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const d
     rc = tc::launch_adj(a, t, stream);
     if (rc) return hip_fail(rc, "totalconv_adj launch");
     tc::EpiArgs e{};
-    e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P;
+    e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax;
     e.U = a.U; e.V = a.V; e.alm = alm; e.blm = blm; e.alm_bar = alm_bar; e.blm_bar = blm_bar;
     rc = tc::launch_adj_epilogue(e, stream);
     return rc ? hip_fail(rc, "totalconv_adj epilogue launch") : TC_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== plans
+//
+// A plan holds, in one device allocation, every detector's tables, its
+// kernel-argument record, the (detector, column, tile) work items sorted by
+// cost (longest first), the queue counter and, for the adjoint, the partial
+// sums.  Its graph is: reset counter -> persistent kernel [-> sky-gradient
+// epilogue over all detectors -> per-detector beam-gradient epilogues].
+
+struct tc_plan_s {
+    int op = 0;
+    int ndet = 0;
+    int sky_lmax = 0;
+    tc::Tile tile{8, 256};
+    void* dmem = nullptr;
+    size_t dbytes = 0;
+    int nitems = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+namespace {
+
+void destroy_plan(tc_plan_s* p)
+{
+    if (!p) return;
+    // Teardown is best effort: errors here cannot be acted on by the caller.
+    if (p->done) (void)hipEventSynchronize(p->done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->dmem) (void)hipFree(p->dmem);
+    delete p;
+}
+
+int check_detector(int i, const tc_detector& d, int op, int lmax_sky)
+{
+    if (d.lmax < 0 || d.lmax > lmax_sky)
+        return fail(TC_EINVAL, "detector %d: lmax = %d outside [0, lmax_sky = %d]", i, d.lmax, lmax_sky);
+    if (d.mbmax < 0 || d.mbmax > d.lmax)
+        return fail(TC_EINVAL, "detector %d: mbmax = %d outside [0, lmax = %d]", i, d.mbmax, d.lmax);
+    if (int rc = check_rings(d.nring, d.cosbeta)) {
+        g_error = "detector " + std::to_string(i) + ": " + g_error;
+        return rc;
+    }
+    if (!d.blm || !aligned16(d.blm)) return fail(TC_EINVAL, "detector %d: blm NULL or not 16-byte aligned", i);
+    if (op == TC_OP_FWD && (!d.C || !aligned16(d.C)))
+        return fail(TC_EINVAL, "detector %d: C NULL or not 16-byte aligned", i);
+    if (op == TC_OP_ADJ) {
+        if (!d.Cbar || !aligned16(d.Cbar)) return fail(TC_EINVAL, "detector %d: Cbar NULL or misaligned", i);
+        if (d.blm_bar && !aligned16(d.blm_bar)) return fail(TC_EINVAL, "detector %d: blm_bar misaligned", i);
+    }
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int lmax_sky, const double* alm,
+                   double* alm_bar, void* stream)
+{
+    g_error.clear();
+    if (!plan) return fail(TC_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (op != TC_OP_FWD && op != TC_OP_ADJ) return fail(TC_EINVAL, "plans support TC_OP_FWD and TC_OP_ADJ only");
+    if (ndet < 1 || !dets) return fail(TC_EINVAL, "ndet must be >= 1 with a detector array");
+    if (lmax_sky < 0 || lmax_sky > TC_LMAX_LIMIT) return fail(TC_EINVAL, "lmax_sky = %d out of range", lmax_sky);
+    if (!alm || !aligned16(alm)) return fail(TC_EINVAL, "alm NULL or not 16-byte aligned");
+    if (alm_bar && !aligned16(alm_bar)) return fail(TC_EINVAL, "alm_bar not 16-byte aligned");
+    for (int i = 0; i < ndet; ++i)
+        if (int rc = check_detector(i, dets[i], op, lmax_sky)) return rc;
+
+    tc_plan_s* p = new tc_plan_s;
+    p->op = op;
+    p->ndet = ndet;
+    p->sky_lmax = lmax_sky;
+    p->tile = default_tile(op, 1 << 20);   // the persistent kernel serves every lmax with one R
+
+    // ---- layout of the plan's device memory
+    std::vector<Layout> lay(ndet);
+    std::vector<size_t> base(ndet);
+    size_t off = 0;
+    long long nitems = 0;
+    for (int i = 0; i < ndet; ++i) {
+        lay[i] = make_layout(op, dets[i].lmax, dets[i].mbmax, dets[i].nring, dets[i].cosbeta, p->tile);
+        base[i] = off;
+        off = align_up(off + lay[i].total);
+        nitems += (long long)lay[i].ncol * lay[i].ntile;
+    }
+    if (nitems > 0x7fffffffLL / 3) { destroy_plan(p); return fail(TC_EUNSUPPORTED, "too many work items"); }
+    const size_t args_off = off;
+    const size_t args_bytes = op == TC_OP_FWD ? sizeof(tc::FwdArgs) * ndet : sizeof(tc::AdjArgs) * ndet;
+    off = align_up(off + args_bytes);
+    const size_t epi_off = off;
+    off = align_up(off + sizeof(tc::EpiArgs) * ndet);
+    const size_t items_off = off;
+    off = align_up(off + sizeof(int) * 3 * (size_t)nitems);
+    const size_t counter_off = off;
+    off = align_up(off + sizeof(int));
+    p->dbytes = off;
+    p->nitems = (int)nitems;
+    int rc = (int)hipMalloc(&p->dmem, p->dbytes);
+    if (rc) { destroy_plan(p); return fail(TC_ENOMEM, "plan: hipMalloc of %zu bytes failed", off); }
+    char* dm = static_cast<char*>(p->dmem);
+
+    // ---- tables, argument records, items (host image of everything up to the U/V gaps)
+    std::vector<tc::FwdArgs> fa(op == TC_OP_FWD ? ndet : 0);
+    std::vector<tc::AdjArgs> aa(op == TC_OP_ADJ ? ndet : 0);
+    std::vector<tc::EpiArgs> ea(ndet);
+    struct Item { int det, col, tile; long long cost; };
+    std::vector<Item> items;
+    items.reserve((size_t)nitems);
+    for (int i = 0; i < ndet; ++i) {
+        const tc_detector& d = dets[i];
+        const Layout& L = lay[i];
+        std::vector<char> img(L.tables_end, 0);
+        build_rings(d.nring, d.cosbeta, img, L);
+        build_slots(d.nring, d.cosbeta, img, L);
+        build_columns(d.lmax, d.mbmax, img, L);
+        rc = (int)hipMemcpy(dm + base[i], img.data(), img.size(), hipMemcpyHostToDevice);
+        if (rc) { destroy_plan(p); return hip_fail(rc, "plan: table upload"); }
+        void* ws = dm + base[i];
+        const int* cms = reinterpret_cast<const int*>(img.data() + L.colms);
+        const int* cmb = reinterpret_cast<const int*>(img.data() + L.colmb);
+        for (int c = 0; c < L.ncol; ++c) {
+            const int len = d.lmax - std::max(std::abs(cmb[c]), cms[c]) + 1;
+            for (int t = 0; t < L.ntile; ++t) {
+                const int slots = std::min(p->tile.NT * p->tile.R, L.nslot - t * p->tile.NT * p->tile.R);
+                items.push_back({i, c, t, (long long)len * slots});
+            }
+        }
+        if (op == TC_OP_FWD) {
+            tc::FwdArgs& a = fa[i];
+            a = tc::FwdArgs{};
+            a.lmax = d.lmax; a.mbmax = d.mbmax; a.nring = d.nring; a.nslot = L.nslot; a.ncol = L.ncol;
+            a.ntile = L.ntile; a.sky_lmax = lmax_sky; a.skip_exp = 100;
+            a.ring = ring_ptrs(ws, L, d.nring);
+            a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
+            a.col = col_ptrs(ws, L);
+            a.alm = alm; a.blm = d.blm; a.C = d.C;
+        } else {
+            tc::AdjArgs& a = aa[i];
+            a = tc::AdjArgs{};
+            a.lmax = d.lmax; a.mbmax = d.mbmax; a.nring = d.nring; a.nslot = L.nslot; a.ncol = L.ncol;
+            a.ntile = L.ntile; a.skip_exp = 100;
+            a.ring = ring_ptrs(ws, L, d.nring);
+            a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
+            a.col = col_ptrs(ws, L);
+            a.Cbar = d.Cbar;
+            a.U = reinterpret_cast<double*>(static_cast<char*>(ws) + L.U);
+            a.V = reinterpret_cast<double*>(static_cast<char*>(ws) + L.V);
+            a.P = L.P;
+            tc::EpiArgs& e = ea[i];
+            e = tc::EpiArgs{};
+            e.lmax = d.lmax; e.mbmax = d.mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax_sky;
+            e.U = a.U; e.V = a.V; e.alm = alm; e.blm = d.blm; e.alm_bar = nullptr; e.blm_bar = d.blm_bar;
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::vector<int> it3(3 * items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        it3[3 * k] = items[k].det;
+        it3[3 * k + 1] = items[k].col;
+        it3[3 * k + 2] = items[k].tile;
+    }
+    rc = (int)hipMemcpy(dm + args_off, op == TC_OP_FWD ? (const void*)fa.data() : (const void*)aa.data(), args_bytes,
+                        hipMemcpyHostToDevice);
+    if (!rc && op == TC_OP_ADJ)
+        rc = (int)hipMemcpy(dm + epi_off, ea.data(), sizeof(tc::EpiArgs) * ndet, hipMemcpyHostToDevice);
+    if (!rc) rc = (int)hipMemcpy(dm + items_off, it3.data(), sizeof(int) * it3.size(), hipMemcpyHostToDevice);
+    if (rc) { destroy_plan(p); return hip_fail(rc, "plan: argument upload"); }
+
+    // ---- persistent grid: every resident workgroup slot of the device
+    int dev = 0, cus = 0, per_cu = 0;
+    rc = (int)hipGetDevice(&dev);
+    if (!rc) rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (!rc) rc = tc::queue_occupancy(op, p->tile, &per_cu);
+    if (rc || cus < 1 || per_cu < 1) { destroy_plan(p); return hip_fail(rc ? rc : 1, "plan: occupancy query"); }
+    p->grid = (int)std::min<long long>((long long)cus * per_cu, std::max(nitems, 1LL));
+
+    // ---- capture the graph on a private stream (the caller's stream may be the legacy one)
+    hipStream_t cs = nullptr;
+    rc = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (rc) { destroy_plan(p); return hip_fail(rc, "plan: capture stream"); }
+    rc = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int* counter = reinterpret_cast<int*>(dm + counter_off);
+    const int* d_items = reinterpret_cast<const int*>(dm + items_off);
+    if (!rc) rc = tc::launch_reset_counter(counter, cs);
+    if (!rc && op == TC_OP_FWD)
+        rc = tc::launch_fwd_queue(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, counter,
+                                  p->tile, p->grid, cs);
+    if (!rc && op == TC_OP_ADJ) {
+        rc = tc::launch_adj_queue(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items, p->nitems, counter,
+                                  p->tile, p->grid, cs);
+        if (!rc && alm_bar)
+            rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
+                                          cs);
+        for (int i = 0; i < ndet && !rc; ++i)
+            if (dets[i].blm_bar) rc = tc::launch_adj_beam(ea[i], cs);
+    }
+    hipGraph_t g = nullptr;
+    const int rc_end = (int)hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    p->graph = g;
+    if (rc || rc_end) { destroy_plan(p); return hip_fail(rc ? rc : rc_end, "plan: graph capture"); }
+    rc = (int)hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (!rc) rc = (int)hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (rc) { destroy_plan(p); return hip_fail(rc, "plan: graph instantiation"); }
+    (void)stream;
+    *plan = p;
+    return TC_OK;
+}
+
+int tc_plan_execute(void* plan, void* stream)
+{
+    g_error.clear();
+    tc_plan_s* p = static_cast<tc_plan_s*>(plan);
+    if (!p || !p->exec) return fail(TC_EINVAL, "invalid plan");
+    int rc = (int)hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (!rc) rc = (int)hipEventRecord(p->done, (hipStream_t)stream);
+    return rc ? hip_fail(rc, "tc_plan_execute") : TC_OK;
+}
+
+size_t tc_plan_device_bytes(void* plan)
+{
+    return plan ? static_cast<tc_plan_s*>(plan)->dbytes : 0;
+}
+
+int tc_plan_tile(void* plan)
+{
+    return plan ? static_cast<tc_plan_s*>(plan)->tile.R : 0;
+}
+
+int tc_plan_destroy(void* plan)
+{
+    destroy_plan(static_cast<tc_plan_s*>(plan));
+    return TC_OK;
 }
 
 }  // extern "C"

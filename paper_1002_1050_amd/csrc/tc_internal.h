@@ -40,6 +40,7 @@ struct WignerArgs {
 
 struct FwdArgs {
     int lmax, mbmax, nring, nslot, ncol, ntile;
+    int sky_lmax;          // packing lmax of the sky (>= lmax; detectors may share one sky)
     int skip_exp;          // accumulate from the first l-block that may hold |d| >= 2^-skip_exp; 0 = always
     RingTables ring;
     const int* slots;      // [nslot][2] (ring j, mirror ring or -1)
@@ -63,6 +64,7 @@ struct AdjArgs {
 
 struct EpiArgs {
     int lmax, mbmax, ntile;
+    int sky_lmax;          // packing lmax of alm and alm_bar
     long long P;
     const double* U;
     const double* V;
@@ -77,6 +79,16 @@ int launch_wigner(const WignerArgs& a, Tile t, void* stream);
 int launch_fwd(const FwdArgs& a, Tile t, void* stream);
 int launch_adj(const AdjArgs& a, Tile t, void* stream);
 int launch_adj_epilogue(const EpiArgs& e, void* stream);
+
+// Batched (persistent) launches: items = (detector, column, tile) triples in queue order.
+int launch_reset_counter(int* counter, void* stream);
+int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+                     void* stream);
+int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+                     void* stream);
+int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream);
+int launch_adj_beam(const EpiArgs& e, void* stream);
+int queue_occupancy(int op, Tile t, int* blocks_per_cu);
 bool tile_supported(int op, Tile t);
 
 }  // namespace tc

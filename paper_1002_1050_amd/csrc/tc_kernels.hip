@@ -190,6 +190,18 @@ __device__ __forceinline__ bool chain_hot(double d, double dp, int E, int skip_e
     return E + e + GROWTH_BITS_PER_STEP * TS > -skip_exp;
 }
 
+// Which l offset in a TB block this lane stages, or -1.  The TB values are spread
+// over the workgroup's waves (TB / (NT/64) lanes per wave) so that no wave carries
+// the staging work alone.
+template <int NT>
+__device__ __forceinline__ int stage_slot(int tid)
+{
+    constexpr int per_wave = TB / (NT / 64);
+    static_assert(per_wave >= 1 && per_wave <= 64 && TB % (NT / 64) == 0, "staging split");
+    const int lane = tid & 63;
+    return lane < per_wave ? (tid >> 6) * per_wave + lane : -1;
+}
+
 __device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
 {
     return (size_t)m * (size_t)(2 * lmax + 1 - m) / 2 + (size_t)l;
@@ -228,10 +240,11 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
 
-    if (tid < TB) {
+    const int st = stage_slot<NT>(tid);
+    if (st >= 0) {
         double A, nB, F2;
-        recursion_coefs(l0 + tid, mb, ms, L, A, nB, F2);
-        cf[0][tid] = make_double4(A, nB, F2, 0.0);
+        recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
+        cf[0][st] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -263,10 +276,10 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
                 }
             }
         }
-        if (tid < TB && kb + 1 < nblk) {
+        if (st >= 0 && kb + 1 < nblk) {
             double A, nB, F2;
-            recursion_coefs(lb + TB + tid, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][tid] = make_double4(A, nB, F2, 0.0);
+            recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
+            cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
         }
         __syncthreads();
     }
@@ -287,7 +300,7 @@ __device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int l, int mb
         const double2* alm = reinterpret_cast<const double2*>(a.alm);
         const double2 b1 = blm[(size_t)(mb + a.mbmax) * (a.lmax + 1) + l];
         const double2 b2 = blm[(size_t)(-mb + a.mbmax) * (a.lmax + 1) + l];
-        const double2 s = alm[packed_index(a.lmax, l, ms)];
+        const double2 s = alm[packed_index(a.sky_lmax, l, ms)];
         w = RawW{b1.x, b1.y, b2.x, b2.y, s.x, s.y};
     }
     return w;
@@ -330,13 +343,12 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
     }
 }
 
+// One (column, ring tile) work item of the forward.  cf: {A, nB, F2, -}, {w1r, w1i, w2r, w2i}
+// per l of the current and the next block.
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
+__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][2])
 {
-    __shared__ double4 cf[2][TB][2];   // {A, nB, F2, -}, {w1r, w1i, w2r, w2i}
     const int tid = threadIdx.x;
-    const int ci = blockIdx.x / a.ntile;
-    const int tile = blockIdx.x - ci * a.ntile;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
@@ -365,12 +377,13 @@ __global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
     scaled = wave_any(scaled);
     bool acc_on = (a.skip_exp <= 0);
 
-    if (tid < TB) {
-        const int l = l0 + tid;
+    const int st = stage_slot<NT>(tid);
+    if (st >= 0) {
+        const int l = l0 + st;
         double A, nB, F2;
         recursion_coefs(l, mb, ms, L, A, nB, F2);
-        cf[0][tid][0] = make_double4(A, nB, F2, 0.0);
-        finish_weights(load_weights_raw(a, l, mb, ms), l, ms, cf[0][tid][1]);
+        cf[0][st][0] = make_double4(A, nB, F2, 0.0);
+        finish_weights(load_weights_raw(a, l, mb, ms), l, ms, cf[0][st][1]);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -378,8 +391,8 @@ __global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
         RawW raw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        const bool stage = (tid < TB) && (kb + 1 < nblk);
-        if (stage) raw = load_weights_raw(a, lb + TB + tid, mb, ms);   // in flight during the block
+        const bool stage = (st >= 0) && (kb + 1 < nblk);
+        if (stage) raw = load_weights_raw(a, lb + TB + st, mb, ms);   // in flight during the block
         for (int s0 = 0; s0 < TB; s0 += TS) {
             if (scaled) {
                 bool any = false;
@@ -406,11 +419,11 @@ __global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
                 fwd_steps<R, NT, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
         }
         if (stage) {
-            const int l = lb + TB + tid;
+            const int l = lb + TB + st;
             double A, nB, F2;
             recursion_coefs(l, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][tid][0] = make_double4(A, nB, F2, 0.0);
-            finish_weights(raw, l, ms, cf[buf ^ 1][tid][1]);
+            cf[buf ^ 1][st][0] = make_double4(A, nB, F2, 0.0);
+            finish_weights(raw, l, ms, cf[buf ^ 1][st][1]);
         }
         __syncthreads();
     }
@@ -428,23 +441,46 @@ __global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
     }
 }
 
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
+{
+    __shared__ double4 cf[2][TB][2];
+    const int ci = blockIdx.x / a.ntile;
+    fwd_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, cf);
+}
+
+// Persistent form: each workgroup takes (detector, column, tile) items from a
+// queue ordered longest first until it is empty.
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
+                                                  int nitems, int* __restrict__ counter)
+{
+    __shared__ double4 cf[2][TB][2];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const FwdArgs a = dets[items[3 * it]];
+        fwd_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], cf);
+    }
+}
+
 // ================================================================== adjoint
 // Per column and l: u_l = sum_j d^l(beta_j) Cbar_j over the direct rings (U)
 // and sum_j d^l(beta_j) Cbar_{-mb,msky}(pi - beta_j) over the mirror rings (V).
 // Each lane sums its R chains in registers; the workgroup then reduces the
 // NT lane sums of TS consecutive l through LDS in a fixed order.
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
+__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, double4 (&cf)[2][TB],
+                                           double4 (&red)[TR][NT])
 {
     static_assert(NT % (4 * TR) == 0 && TS % TR == 0, "reduction split");
     constexpr int G = NT / (4 * TR);   // lanes per reduced value
     static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "reduction group within a wave");
-    __shared__ double4 cf[2][TB];
-    __shared__ double4 red[TR][NT];
-
     const int tid = threadIdx.x;
-    const int ci = blockIdx.x / a.ntile;
-    const int tile = blockIdx.x - ci * a.ntile;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
@@ -494,10 +530,11 @@ __global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
 
-    if (tid < TB) {
+    const int st = stage_slot<NT>(tid);
+    if (st >= 0) {
         double A, nB, F2;
-        recursion_coefs(l0 + tid, mb, ms, L, A, nB, F2);
-        cf[0][tid] = make_double4(A, nB, F2, 0.0);
+        recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
+        cf[0][st] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -581,14 +618,43 @@ __global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
                 }
             }
         }
-        if (tid < TB && kb + 1 < nblk) {
+        if (st >= 0 && kb + 1 < nblk) {
             double A, nB, F2;
-            recursion_coefs(lb + TB + tid, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][tid] = make_double4(A, nB, F2, 0.0);
+            recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
+            cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
         }
         __syncthreads();
     }
 }
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
+{
+    __shared__ double4 cf[2][TB];
+    __shared__ double4 red[TR][NT];
+    const int ci = blockIdx.x / a.ntile;
+    adj_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, cf, red);
+}
+
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
+                                                  int nitems, int* __restrict__ counter)
+{
+    __shared__ double4 cf[2][TB];
+    __shared__ double4 red[TR][NT];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const AdjArgs a = dets[items[3 * it]];
+        adj_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], cf, red);
+    }
+}
+
+__global__ void k_reset_counter(int* counter) { counter[0] = 0; }
 
 // u(mb, ms, l) = sum_tiles U[mb] + (-1)^(l-ms) sum_tiles V[-mb], defined for l >= max(|mb|, ms)
 __device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int l, size_t k)
@@ -606,15 +672,11 @@ __device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int
     return make_double2(ur + sg * vr, ui + sg * vi);
 }
 
-// alm_bar_{l,ms} = sum_mb b_{l,mb} u(mb, ms, l)
-__global__ void __launch_bounds__(256) k_adj_sky(const EpiArgs e)
+// Adds sum_mb b_{l,mb} u(mb, ms, l) of one detector to (ar, ai).
+__device__ __forceinline__ void sky_grad_terms(const EpiArgs& e, int ms, int l, double& ar, double& ai)
 {
-    const int ms = blockIdx.y;
-    const int l = ms + blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > e.lmax) return;
     const size_t k = packed_index(e.lmax, l, ms);
     const double2* blm = reinterpret_cast<const double2*>(e.blm);
-    double ar = 0.0, ai = 0.0;
     for (int mb = -e.mbmax; mb <= e.mbmax; ++mb) {
         if (l < abs(mb)) continue;
         const double2 u = u_value(e, mb, ms, l, k);
@@ -622,7 +684,32 @@ __global__ void __launch_bounds__(256) k_adj_sky(const EpiArgs e)
         ar += b.x * u.x - b.y * u.y;
         ai += b.x * u.y + b.y * u.x;
     }
-    reinterpret_cast<double2*>(e.alm_bar)[k] = make_double2(ar, ai);
+}
+
+// alm_bar_{l,ms} = sum_mb b_{l,mb} u(mb, ms, l)
+__global__ void __launch_bounds__(256) k_adj_sky(const EpiArgs e)
+{
+    const int ms = blockIdx.y;
+    const int l = ms + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > e.sky_lmax) return;
+    double ar = 0.0, ai = 0.0;
+    if (l <= e.lmax) sky_grad_terms(e, ms, l, ar, ai);
+    reinterpret_cast<double2*>(e.alm_bar)[packed_index(e.sky_lmax, l, ms)] = make_double2(ar, ai);
+}
+
+// Batched form: the sky gradient sums every detector in a fixed order.
+__global__ void __launch_bounds__(256) k_adj_sky_multi(const EpiArgs* __restrict__ eps, int ndet, int sky_lmax,
+                                                       double* __restrict__ alm_bar)
+{
+    const int ms = blockIdx.y;
+    const int l = ms + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > sky_lmax) return;
+    double ar = 0.0, ai = 0.0;
+    for (int dt = 0; dt < ndet; ++dt) {
+        const EpiArgs e = eps[dt];
+        if (l <= e.lmax && ms <= e.lmax) sky_grad_terms(e, ms, l, ar, ai);
+    }
+    reinterpret_cast<double2*>(alm_bar)[packed_index(sky_lmax, l, ms)] = make_double2(ar, ai);
 }
 
 // blm_bar_{l,mb} = sum_{ms <= l} s_{l,ms} conj(u(mb, ms, l))
@@ -640,9 +727,8 @@ __global__ void __launch_bounds__(256) k_adj_beam(const EpiArgs e)
     double br = 0.0, bi = 0.0;
 #pragma unroll 4
     for (int ms = 0; ms <= l; ++ms) {
-        const size_t k = packed_index(e.lmax, l, ms);
-        const double2 u = u_value(e, mb, ms, l, k);
-        const double2 s = alm[k];
+        const double2 u = u_value(e, mb, ms, l, packed_index(e.lmax, l, ms));
+        const double2 s = alm[packed_index(e.sky_lmax, l, ms)];
         br += s.x * u.x + s.y * u.y;
         bi += s.y * u.x - s.x * u.y;
     }
@@ -701,7 +787,7 @@ int launch_adj_epilogue(const EpiArgs& e, void* stream)
 {
     const int nt = 256;
     if (e.alm_bar) {
-        dim3 grid((e.lmax + 1 + nt - 1) / nt, e.lmax + 1);
+        dim3 grid((e.sky_lmax + 1 + nt - 1) / nt, e.sky_lmax + 1);
         hipLaunchKernelGGL(k_adj_sky, grid, dim3(nt), 0, (hipStream_t)stream, e);
         const int rc = (int)hipGetLastError();
         if (rc) return rc;
@@ -713,6 +799,76 @@ int launch_adj_epilogue(const EpiArgs& e, void* stream)
         if (rc) return rc;
     }
     return 0;
+}
+
+int launch_adj_beam(const EpiArgs& e, void* stream)
+{
+    const int nt = 256;
+    dim3 grid((e.lmax + 1 + nt - 1) / nt, 2 * e.mbmax + 1);
+    hipLaunchKernelGGL(k_adj_beam, grid, dim3(nt), 0, (hipStream_t)stream, e);
+    return (int)hipGetLastError();
+}
+
+int launch_reset_counter(int* counter, void* stream)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, (hipStream_t)stream, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+                     void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    switch (t.R) {
+    case 2: hipLaunchKernelGGL((k_fwd_queue<2, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    case 4: hipLaunchKernelGGL((k_fwd_queue<4, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    case 8: hipLaunchKernelGGL((k_fwd_queue<8, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+                     void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    switch (t.R) {
+    case 2: hipLaunchKernelGGL((k_adj_queue<2, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    case 4: hipLaunchKernelGGL((k_adj_queue<4, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    case 8: hipLaunchKernelGGL((k_adj_queue<8, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream)
+{
+    const int nt = 256;
+    dim3 grid((sky_lmax + 1 + nt - 1) / nt, sky_lmax + 1);
+    hipLaunchKernelGGL(k_adj_sky_multi, grid, dim3(nt), 0, (hipStream_t)stream, eps, ndet, sky_lmax, alm_bar);
+    return (int)hipGetLastError();
+}
+
+// Resident workgroups per CU of the persistent kernels (for sizing their grid).
+int queue_occupancy(int op, Tile t, int* blocks_per_cu)
+{
+    hipError_t rc = hipErrorInvalidValue;
+    int n = 0;
+    if (op == 1) {
+        switch (t.R) {
+        case 2: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<2, 256>, 256, 0); break;
+        case 4: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<4, 256>, 256, 0); break;
+        case 8: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<8, 256>, 256, 0); break;
+        }
+    } else if (op == 2) {
+        switch (t.R) {
+        case 2: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<2, 256>, 256, 0); break;
+        case 4: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<4, 256>, 256, 0); break;
+        case 8: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<8, 256>, 256, 0); break;
+        }
+    }
+    *blocks_per_cu = n;
+    return (int)rc;
 }
 
 }  // namespace tc
