@@ -36,6 +36,11 @@ constexpr int GROWTH_BITS_PER_STEP = 16;
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
+// Minimum resident waves per SIMD asked of the compiler for R chains per lane
+// (bounds the VGPR budget: 512 / waves).
+template <int R>
+constexpr int min_waves() { return R >= 8 ? 2 : (R >= 4 ? 3 : 4); }
+
 // ------------------------------------------------------------- double-double
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
 {
@@ -442,7 +447,7 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
 }
 
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
+__global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd(const FwdArgs a)
 {
     __shared__ double4 cf[2][TB][2];
     const int ci = blockIdx.x / a.ntile;
@@ -452,7 +457,7 @@ __global__ void __launch_bounds__(NT) k_fwd(const FwdArgs a)
 // Persistent form: each workgroup takes (detector, column, tile) items from a
 // queue ordered longest first until it is empty.
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
+__global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
                                                   int nitems, int* __restrict__ counter)
 {
     __shared__ double4 cf[2][TB][2];
@@ -460,7 +465,7 @@ __global__ void __launch_bounds__(NT) k_fwd_queue(const FwdArgs* __restrict__ de
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        const int it = __builtin_amdgcn_readfirstlane(next);   // uniform: arguments go to SGPRs
         __syncthreads();
         if (it >= nitems) break;
         const FwdArgs a = dets[items[3 * it]];
@@ -471,16 +476,35 @@ __global__ void __launch_bounds__(NT) k_fwd_queue(const FwdArgs* __restrict__ de
 // ================================================================== adjoint
 // Per column and l: u_l = sum_j d^l(beta_j) Cbar_j over the direct rings (U)
 // and sum_j d^l(beta_j) Cbar_{-mb,msky}(pi - beta_j) over the mirror rings (V).
-// Each lane sums its R chains in registers; the workgroup then reduces the
-// NT lane sums of TS consecutive l through LDS in a fixed order.
-template <int R, int NT>
-__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, double4 (&cf)[2][TB],
-                                           double4 (&red)[TR][NT])
+// Each lane sums its R chains in registers.  Every TR steps a wave reduces its
+// 64 lane sums of the 4 values per l through a wave-private LDS region (no
+// workgroup barrier); the waves' totals of a TB block are added in a fixed
+// order after the block's barrier and written out.  Deterministic throughout.
+
+// Order the wave's LDS writes before its own later reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync()
 {
-    static_assert(NT % (4 * TR) == 0 && TS % TR == 0, "reduction split");
-    constexpr int G = NT / (4 * TR);   // lanes per reduced value
-    static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "reduction group within a wave");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NT>
+struct AdjShared {
+    double4 cf[2][TB];                 // {A, nB, F2, -}
+    double4 red[NT / 64][TR][64];      // per wave: lane sums of TR steps
+    double wsum[2][NT / 64][TB][4];    // per TB block parity, wave, step: reduced {P1r, P1i, P2r, P2i}
+};
+
+template <int R, int NT>
+__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT>& sh_)
+{
+    static_assert(TS % TR == 0 && TR * 4 <= 64 && 64 % (TR * 4) == 0, "wave reduction split");
+    constexpr int NW = NT / 64;
+    constexpr int GL = 64 / (TR * 4);  // lanes per reduced value within a wave
+    static_assert(TB * 4 <= NT, "cross-wave sum needs TB*4 threads");
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
@@ -524,7 +548,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, d
 #pragma unroll
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
-    bool acc_on = (a.skip_exp <= 0);
+    bool acc_on = (a.skip_exp <= 0);    // wave-uniform
 
     double2* U = reinterpret_cast<double2*>(a.U) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
@@ -534,7 +558,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, d
     if (st >= 0) {
         double A, nB, F2;
         recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
-        cf[0][st] = make_double4(A, nB, F2, 0.0);
+        sh_.cf[0][st] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -557,50 +581,44 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, d
                 bool hot = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) hot |= chain_hot(d[r], dp[r], E[r], a.skip_exp);
-                acc_on = __syncthreads_or(hot) != 0;      // workgroup-uniform
+                acc_on = wave_any(hot);
             }
             if (acc_on) {
                 for (int h = 0; h < TS; h += TR) {
 #pragma unroll
-                for (int t = 0; t < TR; ++t) {
-                    const double4 k = cf[buf][s0 + h + t];
-                    double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+                    for (int t = 0; t < TR; ++t) {
+                        const double4 k = sh_.cf[buf][s0 + h + t];
+                        double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        p1r = fma(d[r], g1r[r], p1r);
-                        p1i = fma(d[r], g1i[r], p1i);
-                        p2r = fma(d[r], g2r[r], p2r);
-                        p2i = fma(d[r], g2i[r], p2i);
-                        const double u = fma(x[r], k.x, k.y);
-                        const double dn = fma(-k.z, dp[r], u * d[r]);
-                        dp[r] = d[r];
-                        d[r] = dn;
+                        for (int r = 0; r < R; ++r) {
+                            p1r = fma(d[r], g1r[r], p1r);
+                            p1i = fma(d[r], g1i[r], p1i);
+                            p2r = fma(d[r], g2r[r], p2r);
+                            p2i = fma(d[r], g2i[r], p2i);
+                            const double u = fma(x[r], k.x, k.y);
+                            const double dn = fma(-k.z, dp[r], u * d[r]);
+                            dp[r] = d[r];
+                            d[r] = dn;
+                        }
+                        sh_.red[wave][t][lane] = make_double4(p1r, p1i, p2r, p2i);
                     }
-                    red[t][tid] = make_double4(p1r, p1i, p2r, p2i);
-                }
-                __syncthreads();
-                {
-                    const int o = tid / G, sub = tid - o * G;
-                    const int t = o >> 2, comp = o & 3;
-                    double v = 0.0;
-                    for (int n = sub; n < NT; n += G) {
-                        const double4 q = red[t][n];
-                        v += comp == 0 ? q.x : comp == 1 ? q.y : comp == 2 ? q.z : q.w;
-                    }
+                    wave_lds_sync();
+                    // lane -> value o = (step t, component c); GL lanes per value
+                    const int o = lane / GL, sub = lane - o * GL;
+                    const int t = o >> 2, c = o & 3;
+                    const double* src = reinterpret_cast<const double*>(&sh_.red[wave][t][0]) + c;
+                    double v = src[4 * sub];
 #pragma unroll
-                    for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
-                    const int l = lb + s0 + h + t;
-                    if (sub == 0 && l <= L) {
-                        double* dst = reinterpret_cast<double*>(comp < 2 ? U : V) + 2 * (urow + l) + (comp & 1);
-                        *dst = v;
-                    }
-                }
-                __syncthreads();
+                    for (int i = 1; i < 64 / GL; ++i) v += src[4 * (sub + i * GL)];
+#pragma unroll
+                    for (int off = 1; off < GL; off <<= 1) v += __shfl_xor(v, off);
+                    if (sub == 0) sh_.wsum[buf][wave][s0 + h + t][c] = v;
+                    wave_lds_sync();
                 }
             } else {
 #pragma unroll
                 for (int t = 0; t < TS; ++t) {
-                    const double4 k = cf[buf][s0 + t];
+                    const double4 k = sh_.cf[buf][s0 + t];
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const double u = fma(x[r], k.x, k.y);
@@ -609,48 +627,50 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, d
                         d[r] = dn;
                     }
                 }
-                if (tid < TS) {
-                    const int l = lb + s0 + tid;
-                    if (l <= L) {
-                        U[urow + l] = make_double2(0.0, 0.0);
-                        V[urow + l] = make_double2(0.0, 0.0);
-                    }
-                }
+                if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
             }
         }
         if (st >= 0 && kb + 1 < nblk) {
             double A, nB, F2;
             recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
+            sh_.cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
         }
         __syncthreads();
+        // totals of block kb: the waves' sums in a fixed order (the buffer of the
+        // other parity is being filled by the next block meanwhile)
+        if (tid < TB * 4) {
+            const int t = tid >> 2, c = tid & 3;
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) v += sh_.wsum[buf][w][t][c];
+            const int l = lb + t;
+            if (l <= L) reinterpret_cast<double*>(c < 2 ? U : V)[2 * (urow + l) + (c & 1)] = v;
+        }
     }
 }
 
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_adj(const AdjArgs a)
+__global__ void __launch_bounds__(NT, min_waves<R>()) k_adj(const AdjArgs a)
 {
-    __shared__ double4 cf[2][TB];
-    __shared__ double4 red[TR][NT];
+    __shared__ AdjShared<NT> sh;
     const int ci = blockIdx.x / a.ntile;
-    adj_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, cf, red);
+    adj_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, sh);
 }
 
 template <int R, int NT>
-__global__ void __launch_bounds__(NT) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
+__global__ void __launch_bounds__(NT, min_waves<R>()) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
                                                   int nitems, int* __restrict__ counter)
 {
-    __shared__ double4 cf[2][TB];
-    __shared__ double4 red[TR][NT];
+    __shared__ AdjShared<NT> sh;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        const int it = __builtin_amdgcn_readfirstlane(next);   // uniform: arguments go to SGPRs
         __syncthreads();
         if (it >= nitems) break;
         const AdjArgs a = dets[items[3 * it]];
-        adj_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], cf, red);
+        adj_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], sh);
     }
 }
 
