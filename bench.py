@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--batched-reps", type=int, default=3,
                    help="interleaved repetitions of the sixteen-detector batched-vs-plain comparison (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
+    p.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                   help="first run one device-to-device copy of this many GiB (a reference kernel of known "
+                        "traffic for hardware byte counters)")
     return p.parse_args()
 
 
@@ -110,24 +113,25 @@ def batched_compare(reps, tune):
         blm = torch.from_numpy(d.blm()).to(dev)
         C = torch.empty((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128, device=dev)
         a_d = torch.from_numpy(truncate_sky(S, alm_h, w.lmax, d.lmax)).to(dev)
-        R = autotune.tune_plain(B.TC_OP_FWD, d.lmax, d.mbmax, x, a_d, blm, reps=1) if tune else 0
+        t = autotune.tune_plain(B.TC_OP_FWD, d.lmax, d.mbmax, x, a_d, blm, reps=1) if tune else (0, 0, 0)
         dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": x, "blm": blm, "C": C})
-        plain.append((d, x, a_d, blm, C, R))
-        log(f"  detector lmax={d.lmax} mbmax={d.mbmax} nring={d.nring} plain R={R or 'default'}")
+        plain.append((d, x, a_d, blm, C, t))
+        log(f"  detector lmax={d.lmax} mbmax={d.mbmax} nring={d.nring} plain tile (R, TB, TR)={t}")
 
     def run_plain():
-        for d, x, a_d, blm, C, R in plain:
-            B.set_tile(B.TC_OP_FWD, R)
+        for d, x, a_d, blm, C, t in plain:
+            B.set_tile_ex(B.TC_OP_FWD, *t)
             B.totalconv_fwd(d.lmax, d.mbmax, x, a_d, blm, out=C)
-        B.set_tile(B.TC_OP_FWD, 0)
+        B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
 
+    tp_ = (0, 0, 0)
     if tune:
-        Rp, tms = autotune.tune_plan(B.TC_OP_FWD, lambda: B.Plan(B.TC_OP_FWD, dets, w.lmax, alm), reps=1,
-                                     key_extra="batched16")
-        log(f"  plan tile R={Rp} (trial ms {tms})")
-        B.set_tile(B.TC_OP_FWD, Rp)
+        tp_, tms = autotune.tune_plan(B.TC_OP_FWD, lambda: B.Plan(B.TC_OP_FWD, dets, w.lmax, alm), reps=1,
+                                      key_extra="batched16")
+        log(f"  plan tile (R, TB, TR)={tp_} (trial ms {tms})")
+    B.set_tile_ex(B.TC_OP_FWD, *tp_)
     plan = B.Plan(B.TC_OP_FWD, dets, w.lmax, alm)
-    B.set_tile(B.TC_OP_FWD, 0)
+    B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     s = torch.cuda.current_stream(dev)
     run_plain()
     plan.execute()
@@ -159,7 +163,8 @@ def batched_compare(reps, tune):
         "speedup_median": float(np.median(ratios)),
         "speedup_min": float(np.min(ratios)),
         "speedup_max": float(np.max(ratios)),
-        "plan_tile_R": plan.tile,
+        "plan_tile": list(tp_) if tune else "built-in",
+        "plan_R": plan.tile,
         "reps": reps,
     }
     plan.close()
@@ -176,6 +181,15 @@ def main():
     from paper_1002_1050_amd import _binding as B
     from paper_1002_1050_amd import synthetic as S
 
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read and written")
+        del src, dst
     w = S.WORKLOADS[args.workload]
     if w.detectors:
         raise SystemExit("batched workloads are timed by bench_batched")
@@ -196,6 +210,17 @@ def main():
     del T
     torch.cuda.synchronize()
     log("set-up done")
+
+    tiles = {"forward": "built-in", "adjoint": "built-in"}
+    if not args.no_tune:
+        from paper_1002_1050_amd import autotune
+        tf = autotune.tune_plain(B.TC_OP_FWD, w.lmax, w.mbmax, x, alm, blm, reps=1)
+        ta = autotune.tune_plain(B.TC_OP_ADJ, w.lmax, w.mbmax, x, alm, blm, G, reps=1)
+        B.set_tile_ex(B.TC_OP_FWD, *tf)
+        B.set_tile_ex(B.TC_OP_ADJ, *ta)
+        tiles = {"forward": list(tf), "adjoint": list(ta)}
+        log(f"autotuned tiles (R, TB, TR): forward {tf}, adjoint {ta}")
+        torch.cuda.empty_cache()
 
     def step():
         B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
@@ -269,6 +294,7 @@ def main():
         "forward_terms_per_s": terms / (fwd_ms * 1e-3),
         "adjoint_terms_per_s": (terms / (adj_ms * 1e-3)) if adj_ms else None,
         "roofline": roofline,
+        "tiles_R_TB_TR": tiles,
     }
     if args.cpu_seconds > 0:
         nring = w.nring
@@ -281,6 +307,8 @@ def main():
         log(f"cpu baseline: oracle on a sample, about {args.cpu_seconds:.0f} s")
         result["cpu_baseline"] = cpu_baseline(w, x, alm_h, blm_h, g_cols, args.cpu_seconds)
         del Gc
+    B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
+    B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
     if args.batched_reps > 0:
         del C, G
         torch.cuda.empty_cache()

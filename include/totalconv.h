@@ -139,8 +139,19 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
  */
 int tc_set_tile(int op, int R);
 
+/*
+ * Full tile selection: R chains per lane, TB values of l per LDS coefficient
+ * block (32 or 64), TR steps per wave reduction of the adjoint's lane sums
+ * (4).  0 keeps the built-in value of a parameter.  Same
+ * scope and rules as tc_set_tile; TC_EINVAL for combinations that are not built.
+ */
+int tc_set_tile_ex(int op, int R, int TB, int TR);
+
 /* The R that the next call of `op` at this lmax would use. */
 int tc_get_tile(int op, int lmax);
+
+/* The full tile (R, TB, TR) that the next call of `op` at this lmax would use. */
+int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR);
 
 /*
  * Batched plan: many detectors -- each with its own beam, mbmax, lmax and ring

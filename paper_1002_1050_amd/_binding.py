@@ -66,6 +66,10 @@ def lib():
             L.tc_set_tile.argtypes = [I, I]
             L.tc_get_tile.restype = I
             L.tc_get_tile.argtypes = [I, I]
+            L.tc_set_tile_ex.restype = I
+            L.tc_set_tile_ex.argtypes = [I, I, I, I]
+            L.tc_get_tile_ex.restype = I
+            L.tc_get_tile_ex.argtypes = [I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
             L.tc_plan_create.restype = I
             L.tc_plan_create.argtypes = [ctypes.POINTER(P), I, I, ctypes.POINTER(TcDetector), I, P, P, P]
             L.tc_plan_execute.restype = I
@@ -214,6 +218,17 @@ def set_tile(op: int, R: int):
 
 def get_tile(op: int, lmax: int) -> int:
     return int(lib().tc_get_tile(op, lmax))
+
+
+def set_tile_ex(op: int, R: int = 0, TB: int = 0, TR: int = 0):
+    """Chains per lane R, l-block TB and adjoint reduction block TR for later calls; 0 = built-in."""
+    _check("tc_set_tile_ex", lib().tc_set_tile_ex(op, R, TB, TR))
+
+
+def get_tile_ex(op: int, lmax: int):
+    R, TB, TR = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check("tc_get_tile_ex", lib().tc_get_tile_ex(op, lmax, ctypes.byref(R), ctypes.byref(TB), ctypes.byref(TR)))
+    return R.value, TB.value, TR.value
 
 
 class Plan:

@@ -1,4 +1,8 @@
-"""Tile autotuner: picks R (chains per lane) for plain calls and batched plans.
+"""Tile autotuner: picks (R, TB, TR) for plain calls and batched plans.
+
+R is the chain block (chains per lane; a workgroup covers 256 R ring slots of a
+column), TB the l block (values of l per LDS coefficient block), TR the
+adjoint's reduction block (steps per wave reduction).
 
 Each candidate runs the real launch (after one untimed warm-up) and is timed with
 HIP events on the stream it runs on; the fastest wins.  Results are cached in a
@@ -12,7 +16,14 @@ import os
 
 from . import _binding as B
 
-CANDIDATES = {B.TC_OP_FWD: (2, 4, 8), B.TC_OP_ADJ: (2, 4, 8)}
+CANDIDATES = {
+    B.TC_OP_FWD: [(r, tb, 4) for tb in (32, 64) for r in (2, 4, 8)],
+    B.TC_OP_ADJ: [(r, tb, 4) for tb in (32, 64) for r in (2, 4, 8)],
+}
+
+
+def _key(t):
+    return "R%d_TB%d_TR%d" % t
 
 
 def _cache_path():
@@ -60,46 +71,47 @@ def _gpu_name():
 
 
 def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=True):
-    """Best R for a plain totalconv_fwd / totalconv_adj call of this shape."""
+    """Best (R, TB, TR) for a plain totalconv_fwd / totalconv_adj call of this shape."""
     key = f"plain:{op}:{lmax}:{mbmax}:{len(cosbeta)}:{_gpu_name()}"
     cache = _load() if use_cache else {}
     if key in cache:
-        return cache[key]["R"]
+        return tuple(cache[key]["tile"])
     times = {}
-    old = B.get_tile(op, lmax)
+    default = B.get_tile_ex(op, lmax)
     try:
-        for R in CANDIDATES[op]:
-            B.set_tile(op, R)
+        for t in CANDIDATES[op]:
+            B.set_tile_ex(op, *t)
             if op == B.TC_OP_FWD:
-                times[R] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
+                times[t] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
             else:
-                times[R] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
+                B.workspace_cache.clear()
+                times[t] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
     finally:
-        B.set_tile(op, 0)
+        B.set_tile_ex(op, 0, 0, 0)
     best = min(times, key=times.get)
     cache = _load()
-    cache[key] = {"R": best, "ms": {str(k): v for k, v in times.items()}, "default_R": old}
+    cache[key] = {"tile": list(best), "ms": {_key(k): v for k, v in times.items()}, "default": list(default)}
     _store(cache)
     return best
 
 
 def tune_plan(op, make_plan, reps=2, use_cache=True, key_extra=""):
-    """Best R for a batched plan; make_plan() builds the plan for the current tile setting."""
+    """Best (R, TB, TR) for a batched plan; make_plan() builds the plan for the current tile."""
     key = f"plan:{op}:{key_extra}:{_gpu_name()}"
     cache = _load() if use_cache else {}
     if key in cache:
-        return cache[key]["R"], cache[key]["ms"]
+        return tuple(cache[key]["tile"]), cache[key]["ms"]
     times = {}
     try:
-        for R in CANDIDATES[op]:
-            B.set_tile(op, R)
+        for t in CANDIDATES[op]:
+            B.set_tile_ex(op, *t)
             plan = make_plan()
-            times[R] = _time(plan.execute, reps)
+            times[t] = _time(plan.execute, reps)
             plan.close()
     finally:
-        B.set_tile(op, 0)
+        B.set_tile_ex(op, 0, 0, 0)
     best = min(times, key=times.get)
     cache = _load()
-    cache[key] = {"R": best, "ms": {str(k): v for k, v in times.items()}}
+    cache[key] = {"tile": list(best), "ms": {_key(k): v for k, v in times.items()}}
     _store(cache)
     return best, cache[key]["ms"]

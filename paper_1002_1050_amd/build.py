@@ -22,6 +22,10 @@ HIP_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions stay off (no FP32 arithmetic here, and the forms are avoided)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit a*b+c fusion: every fused multiply-add is an explicit fma(), so all
+    # tile variants round identically (a fused or split a*b + c*d would depend on
+    # each instantiation's scheduling)
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
 ]
 

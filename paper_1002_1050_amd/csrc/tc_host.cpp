@@ -58,12 +58,21 @@ void split_dd(ld v, double& hi, double& lo)
 
 // ---------------------------------------------------------------- tile choice
 
-int g_tile_override[3] = {0, 0, 0};   // tc_set_tile
+tc::Tile g_tile_override[3] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // tc_set_tile_ex; 0 = built-in
 
 tc::Tile default_tile(int op, int lmax)
 {
-    tc::Tile t{op == TC_OP_WIGNER ? 4 : (lmax >= 256 ? 8 : 2), 256};
-    if (op >= 0 && op < 3 && g_tile_override[op] > 0) t.R = g_tile_override[op];
+    // Built-in choice from a sweep at lmax 4096 / mbmax 14 on MI355X: the forward
+    // prefers 4 chains per lane (3 waves per SIMD) with 64-l blocks, the adjoint 8.
+    tc::Tile t{4, 256, 32, 4};
+    if (op == TC_OP_FWD) t = lmax >= 256 ? tc::Tile{4, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
+    if (op == TC_OP_ADJ) t = lmax >= 256 ? tc::Tile{8, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
+    if (op >= 0 && op < 3) {
+        const tc::Tile& o = g_tile_override[op];
+        if (o.R > 0) t.R = o.R;
+        if (o.TB > 0) t.TB = o.TB;
+        if (o.TR > 0) t.TR = o.TR;
+    }
     return t;
 }
 
@@ -249,19 +258,40 @@ extern "C" {
 
 const char* tc_last_error(void) { return g_error.c_str(); }
 
+int tc_set_tile_ex(int op, int R, int TB, int TR)
+{
+    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
+    if (R < 0 || TB < 0 || TR < 0) return fail(TC_EINVAL, "tc_set_tile: negative tile parameter");
+    const tc::Tile o = g_tile_override[op];
+    g_tile_override[op] = tc::Tile{R, 256, TB, TR};
+    if (!tc::tile_supported(op, default_tile(op, 1 << 20))) {
+        g_tile_override[op] = o;
+        return fail(TC_EINVAL, "tc_set_tile: (R %d, TB %d, TR %d) is not built for op %d", R, TB, TR, op);
+    }
+    return TC_OK;
+}
+
 int tc_set_tile(int op, int R)
 {
     if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
-    if (R != 0 && !tc::tile_supported(op, tc::Tile{R, 256}))
-        return fail(TC_EINVAL, "tc_set_tile: R = %d is not built for op %d", R, op);
-    g_tile_override[op] = R;
-    return TC_OK;
+    const tc::Tile o = g_tile_override[op];
+    return tc_set_tile_ex(op, R, o.TB, o.TR);
 }
 
 int tc_get_tile(int op, int lmax)
 {
     if (op < 0 || op > 2) return 0;
     return default_tile(op, lmax).R;
+}
+
+int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR)
+{
+    if (op < 0 || op > 2 || !R || !TB || !TR) return fail(TC_EINVAL, "tc_get_tile_ex: bad arguments");
+    const tc::Tile t = default_tile(op, lmax);
+    *R = t.R;
+    *TB = t.TB;
+    *TR = t.TR;
+    return TC_OK;
 }
 
 int tc_abi_version(void) { return 1; }
@@ -399,7 +429,7 @@ struct tc_plan_s {
     int op = 0;
     int ndet = 0;
     int sky_lmax = 0;
-    tc::Tile tile{8, 256};
+    tc::Tile tile{8, 256, 32, 4};
     void* dmem = nullptr;
     size_t dbytes = 0;
     int nitems = 0;

@@ -13,6 +13,8 @@ namespace tc {
 struct Tile {
     int R;    // chains per lane
     int NT;   // lanes per workgroup
+    int TB;   // l values per LDS coefficient block
+    int TR;   // adjoint: steps per wave reduction of the lane sums
 };
 
 // Device-resident per-call tables, all inside the caller's workspace.

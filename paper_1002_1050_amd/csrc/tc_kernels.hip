@@ -26,9 +26,9 @@
 namespace tc {
 namespace {
 
-constexpr int TB = 32;        // l values per coefficient block
+// Tile parameters (template arguments): R chains per lane, NT lanes per workgroup,
+// TB values of l per coefficient block, TR steps per wave reduction (adjoint).
 constexpr int TS = 8;         // steps between scale / skip checks
-constexpr int TR = 4;         // adjoint: steps per workgroup reduction of the lane sums
 constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-900
 // A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
 // (F0 <= l+1, |x - F1| < 2, F2 <= 2), which bounds growth inside a TS block.
@@ -40,6 +40,11 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 // (bounds the VGPR budget: 512 / waves).
 template <int R>
 constexpr int min_waves() { return R >= 8 ? 2 : (R >= 4 ? 3 : 4); }
+
+// The adjoint's LDS (about 53 KB per workgroup with TB = 32, 62 KB with TB = 64)
+// caps residency at 3 or 2 workgroups (waves per SIMD) per CU.
+template <int R, int TB>
+constexpr int adj_min_waves() { return min_waves<R>() < (TB >= 64 ? 2 : 3) ? min_waves<R>() : (TB >= 64 ? 2 : 3); }
 
 // ------------------------------------------------------------- double-double
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
@@ -164,41 +169,34 @@ __device__ __forceinline__ int chain_exponent(double d, double dp)
     return max(e1, e2);
 }
 
-// Renormalise a scaled chain (E < 0): fold into plain doubles once the true
-// value reaches 2^-900, else bring the significand back near 1.  Returns the
-// power of two applied to (d, dp) so the caller can apply it to its sums.
-__device__ __forceinline__ int renorm(double& d, double& dp, int& E)
+// One scale / skip check of a chain, every TS steps.  From the exponent e of
+// max(|d|, |d_prev|) it takes the true exponent te = E + e of the chain.
+//  - rescale: a scaled chain (E < 0) is folded into plain doubles once te reaches
+//    -900 (k = E), otherwise brought back to a significand near 1 (k = -e); the
+//    power of two k applied to (d, d_prev) is returned for the caller's sums.
+//  - returns whether |d| may reach 2^-skip_exp within the next TS steps.
+// Branch-free per chain; the callers' conditions are wave-uniform.
+__device__ __forceinline__ bool check_chain(double& d, double& dp, int& E, int skip_exp, bool rescale, int& k)
 {
-    if (E >= 0) return 0;
+    const bool nz = (d != 0.0) | (dp != 0.0);
     const int e = chain_exponent(d, dp);
-    int k;
-    if (d == 0.0 && dp == 0.0) {
-        k = 0;
-    } else if (E + e >= FOLD_EXP) {
-        k = E;
-        E = 0;
-    } else {
-        k = -e;
-        E += e;
+    const int te = E + e;
+    k = 0;
+    if (rescale) {
+        const bool sc = nz & (E < 0);
+        const bool fold = te >= FOLD_EXP;
+        k = sc ? (fold ? E : -e) : 0;
+        E = sc ? (fold ? 0 : te) : E;
+        d = ldexp(d, k);
+        dp = ldexp(dp, k);
     }
-    d = ldexp(d, k);
-    dp = ldexp(dp, k);
-    return k;
-}
-
-// Could |d| reach 2^-eps_exp within the next TS steps?  (True exponent E + e
-// plus the growth bound.)
-__device__ __forceinline__ bool chain_hot(double d, double dp, int E, int skip_exp)
-{
-    if (d == 0.0 && dp == 0.0) return false;
-    const int e = chain_exponent(d, dp);
-    return E + e + GROWTH_BITS_PER_STEP * TS > -skip_exp;
+    return nz & (te + GROWTH_BITS_PER_STEP * TS > -skip_exp);
 }
 
 // Which l offset in a TB block this lane stages, or -1.  The TB values are spread
 // over the workgroup's waves (TB / (NT/64) lanes per wave) so that no wave carries
 // the staging work alone.
-template <int NT>
+template <int NT, int TB>
 __device__ __forceinline__ int stage_slot(int tid)
 {
     constexpr int per_wave = TB / (NT / 64);
@@ -213,7 +211,7 @@ __device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
 }
 
 // ================================================================ wigner_d_rings
-template <int R, int NT>
+template <int R, int NT, int TB>
 __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
 {
     __shared__ double4 cf[2][TB];
@@ -245,7 +243,7 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
 
-    const int st = stage_slot<NT>(tid);
+    const int st = stage_slot<NT, TB>(tid);
     if (st >= 0) {
         double A, nB, F2;
         recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
@@ -261,7 +259,8 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
                 bool any = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    renorm(d[r], dp[r], E[r]);
+                    int k;
+                    check_chain(d[r], dp[r], E[r], 0, true, k);
                     any |= (E[r] < 0);
                 }
                 scaled = wave_any(any);
@@ -322,7 +321,7 @@ __device__ __forceinline__ void finish_weights(const RawW& w, int l, int ms, dou
     out = make_double4(w1r, w1i, w2r, w2i);
 }
 
-template <int R, int NT, bool ACC>
+template <int R, bool ACC>
 __device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
                                           const double (&x)[R], double (&d)[R], double (&dp)[R],
                                           double (&c1r)[R], double (&c1i)[R], double (&c2r)[R], double (&c2i)[R])
@@ -350,7 +349,7 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
 
 // One (column, ring tile) work item of the forward.  cf: {A, nB, F2, -}, {w1r, w1i, w2r, w2i}
 // per l of the current and the next block.
-template <int R, int NT>
+template <int R, int NT, int TB>
 __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][2])
 {
     const int tid = threadIdx.x;
@@ -382,7 +381,7 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     scaled = wave_any(scaled);
     bool acc_on = (a.skip_exp <= 0);
 
-    const int st = stage_slot<NT>(tid);
+    const int st = stage_slot<NT, TB>(tid);
     if (st >= 0) {
         const int l = l0 + st;
         double A, nB, F2;
@@ -399,29 +398,25 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
         const bool stage = (st >= 0) && (kb + 1 < nblk);
         if (stage) raw = load_weights_raw(a, lb + TB + st, mb, ms);   // in flight during the block
         for (int s0 = 0; s0 < TB; s0 += TS) {
-            if (scaled) {
-                bool any = false;
+            if (scaled || !acc_on) {
+                bool any = false, hot = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int k = renorm(d[r], dp[r], E[r]);
-                    if (k != 0) {
+                    int k;
+                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, scaled, k);
+                    if (scaled && acc_on) {   // sums in the chain's scaled units follow it
                         c1r[r] = ldexp(c1r[r], k); c1i[r] = ldexp(c1i[r], k);
                         c2r[r] = ldexp(c2r[r], k); c2i[r] = ldexp(c2i[r], k);
                     }
                     any |= (E[r] < 0);
                 }
-                scaled = wave_any(any);
-            }
-            if (!acc_on) {
-                bool hot = false;
-#pragma unroll
-                for (int r = 0; r < R; ++r) hot |= chain_hot(d[r], dp[r], E[r], a.skip_exp);
-                acc_on = wave_any(hot);
+                if (scaled) scaled = wave_any(any);
+                if (!acc_on) acc_on = wave_any(hot);
             }
             if (acc_on)
-                fwd_steps<R, NT, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                fwd_steps<R, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
             else
-                fwd_steps<R, NT, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                fwd_steps<R, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
         }
         if (stage) {
             const int l = lb + TB + st;
@@ -446,17 +441,17 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     }
 }
 
-template <int R, int NT>
+template <int R, int NT, int TB>
 __global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd(const FwdArgs a)
 {
     __shared__ double4 cf[2][TB][2];
     const int ci = blockIdx.x / a.ntile;
-    fwd_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, cf);
+    fwd_column<R, NT, TB>(a, ci, blockIdx.x - ci * a.ntile, cf);
 }
 
 // Persistent form: each workgroup takes (detector, column, tile) items from a
 // queue ordered longest first until it is empty.
-template <int R, int NT>
+template <int R, int NT, int TB>
 __global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
                                                   int nitems, int* __restrict__ counter)
 {
@@ -469,7 +464,7 @@ __global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd_queue(const FwdArgs*
         __syncthreads();
         if (it >= nitems) break;
         const FwdArgs a = dets[items[3 * it]];
-        fwd_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], cf);
+        fwd_column<R, NT, TB>(a, items[3 * it + 1], items[3 * it + 2], cf);
     }
 }
 
@@ -489,19 +484,48 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NT>
+// Within a quad of lanes: the value of lane ^ 1 or lane ^ 2 (DPP quad permutes, no LDS).
+template <int OFF>
+__device__ __forceinline__ double quad_xor(double v)
+{
+    static_assert(OFF == 1 || OFF == 2, "quad permutes only");
+    constexpr int ctrl = OFF == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave reduction buffer.  LDS serves 64-bit accesses 16 lanes at a time, so the
+// layout keeps every group of 16 lanes on 16 distinct bank pairs:
+//  - value v (step t, component c) owns a row of RED_ROW doubles (RED_ROW = 1 mod 16);
+//  - within a row the 64 lane sums sit in chunks of PER = 4 TR lanes, chunk k at
+//    k * red_chunk<TR>() (chunk stride = PER + 16 / GL), so a reading lane
+//    (value o, part k) starts at o * RED_ROW + k * chunk, and for the 16 lanes of a
+//    group (o mod 4, k) these starts are distinct modulo 16 doubles;
+//  - a writing lane n stores at v * RED_ROW + (n / PER) * chunk + n % PER: 16
+//    consecutive lanes write 16 consecutive doubles.
+constexpr int RED_ROW = 81;
+
+template <int TR>
+constexpr int red_chunk() { return 4 * TR + 16 / (64 / (4 * TR)); }
+
+template <int NT, int TB, int TR>
 struct AdjShared {
-    double4 cf[2][TB];                 // {A, nB, F2, -}
-    double4 red[NT / 64][TR][64];      // per wave: lane sums of TR steps
-    double wsum[2][NT / 64][TB][4];    // per TB block parity, wave, step: reduced {P1r, P1i, P2r, P2i}
+    double4 cf[2][TB];                          // {A, nB, F2, -}
+    double red[NT / 64][4 * TR][RED_ROW];       // per wave: value (step t, component c) x lane
+    double wsum[2][NT / 64][TB][4];             // per TB block parity, wave, step: reduced {P1r, P1i, P2r, P2i}
 };
 
-template <int R, int NT>
-__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT>& sh_)
+template <int R, int NT, int TB, int TR>
+__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT, TB, TR>& sh_)
 {
     static_assert(TS % TR == 0 && TR * 4 <= 64 && 64 % (TR * 4) == 0, "wave reduction split");
     constexpr int NW = NT / 64;
-    constexpr int GL = 64 / (TR * 4);  // lanes per reduced value within a wave
+    constexpr int GL = 64 / (TR * 4);  // lanes per reduced value within a wave (a quad or less)
+    static_assert(GL <= 4, "in-quad combine");
+    constexpr int PER = 64 / GL;       // lane sums each reducing lane adds up
+    constexpr int CH = red_chunk<TR>();
+    static_assert(GL * CH <= RED_ROW, "reduction row");
     static_assert(TB * 4 <= NT, "cross-wave sum needs TB*4 threads");
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -554,7 +578,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
 
-    const int st = stage_slot<NT>(tid);
+    const int st = stage_slot<NT, TB>(tid);
     if (st >= 0) {
         double A, nB, F2;
         recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
@@ -566,22 +590,18 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
         for (int s0 = 0; s0 < TB; s0 += TS) {
-            if (scaled) {
-                bool any = false;
+            if (scaled || !acc_on) {
+                bool any = false, hot = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const bool was = E[r] < 0;
-                    renorm(d[r], dp[r], E[r]);
+                    int k;
+                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, scaled, k);
                     if (was && E[r] == 0) load_g(r);
                     any |= (E[r] < 0);
                 }
-                scaled = wave_any(any);
-            }
-            if (!acc_on) {
-                bool hot = false;
-#pragma unroll
-                for (int r = 0; r < R; ++r) hot |= chain_hot(d[r], dp[r], E[r], a.skip_exp);
-                acc_on = wave_any(hot);
+                if (scaled) scaled = wave_any(any);
+                if (!acc_on) acc_on = wave_any(hot);
             }
             if (acc_on) {
                 for (int h = 0; h < TS; h += TR) {
@@ -600,19 +620,29 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                             dp[r] = d[r];
                             d[r] = dn;
                         }
-                        sh_.red[wave][t][lane] = make_double4(p1r, p1i, p2r, p2i);
+                        const int wpos = (lane / PER) * CH + lane % PER;
+                        sh_.red[wave][4 * t + 0][wpos] = p1r;
+                        sh_.red[wave][4 * t + 1][wpos] = p1i;
+                        sh_.red[wave][4 * t + 2][wpos] = p2r;
+                        sh_.red[wave][4 * t + 3][wpos] = p2i;
                     }
                     wave_lds_sync();
-                    // lane -> value o = (step t, component c); GL lanes per value
+                    // lane -> value o = 4 t + c, part sub of GL; adds PER consecutive lane sums
                     const int o = lane / GL, sub = lane - o * GL;
-                    const int t = o >> 2, c = o & 3;
-                    const double* src = reinterpret_cast<const double*>(&sh_.red[wave][t][0]) + c;
-                    double v = src[4 * sub];
+                    const double* src = &sh_.red[wave][o][sub * CH];
+                    // all reads in flight at once, then a fixed binary tree
+                    double part[PER];
 #pragma unroll
-                    for (int i = 1; i < 64 / GL; ++i) v += src[4 * (sub + i * GL)];
+                    for (int i = 0; i < PER; ++i) part[i] = src[i];
 #pragma unroll
-                    for (int off = 1; off < GL; off <<= 1) v += __shfl_xor(v, off);
-                    if (sub == 0) sh_.wsum[buf][wave][s0 + h + t][c] = v;
+                    for (int w2 = 1; w2 < PER; w2 <<= 1) {
+#pragma unroll
+                        for (int i = 0; i < PER; i += 2 * w2) part[i] += part[i + w2];
+                    }
+                    double v = part[0];
+                    if (GL >= 2) v += quad_xor<1>(v);
+                    if (GL >= 4) v += quad_xor<2>(v);
+                    if (sub == 0) sh_.wsum[buf][wave][s0 + h + (o >> 2)][o & 3] = v;
                     wave_lds_sync();
                 }
             } else {
@@ -649,19 +679,19 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     }
 }
 
-template <int R, int NT>
-__global__ void __launch_bounds__(NT, min_waves<R>()) k_adj(const AdjArgs a)
+template <int R, int NT, int TB, int TR>
+__global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjArgs a)
 {
-    __shared__ AdjShared<NT> sh;
+    __shared__ AdjShared<NT, TB, TR> sh;
     const int ci = blockIdx.x / a.ntile;
-    adj_column<R, NT>(a, ci, blockIdx.x - ci * a.ntile, sh);
+    adj_column<R, NT, TB, TR>(a, ci, blockIdx.x - ci * a.ntile, sh);
 }
 
-template <int R, int NT>
-__global__ void __launch_bounds__(NT, min_waves<R>()) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
+template <int R, int NT, int TB, int TR>
+__global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
                                                   int nitems, int* __restrict__ counter)
 {
-    __shared__ AdjShared<NT> sh;
+    __shared__ AdjShared<NT, TB, TR> sh;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -670,7 +700,7 @@ __global__ void __launch_bounds__(NT, min_waves<R>()) k_adj_queue(const AdjArgs*
         __syncthreads();
         if (it >= nitems) break;
         const AdjArgs a = dets[items[3 * it]];
-        adj_column<R, NT>(a, items[3 * it + 1], items[3 * it + 2], sh);
+        adj_column<R, NT, TB, TR>(a, items[3 * it + 1], items[3 * it + 2], sh);
     }
 }
 
@@ -764,43 +794,50 @@ int launch_grid(void (*kern)(Args), const Args& a, int blocks, int nt, void* str
 
 }  // namespace
 
+// Built tile variants.  Forward and adjoint: R in {2, 4, 8}, TB in {32, 64};
+// adjoint reductions every TR = 4 steps.  Wigner: R in {1, 4}, TB = 32.
 bool tile_supported(int op, Tile t)
 {
     if (t.NT != 256) return false;
-    if (op == 0) return t.R == 1 || t.R == 4;
-    return t.R == 2 || t.R == 4 || t.R == 8;
+    if (op == 0) return (t.R == 1 || t.R == 4) && t.TB == 32;
+    const bool r_ok = t.R == 2 || t.R == 4 || t.R == 8;
+    const bool tb_ok = t.TB == 32 || t.TB == 64;
+    if (op == 1) return r_ok && tb_ok;
+    if (op == 2) return r_ok && tb_ok && t.TR == 4;
+    return false;
 }
 
 int launch_wigner(const WignerArgs& a, Tile t, void* stream)
 {
     const int blocks = a.npair * a.ntile;
     switch (t.R) {
-    case 1: return launch_grid(k_wigner<1, 256>, a, blocks, 256, stream);
-    case 4: return launch_grid(k_wigner<4, 256>, a, blocks, 256, stream);
+    case 1: return launch_grid(k_wigner<1, 256, 32>, a, blocks, 256, stream);
+    case 4: return launch_grid(k_wigner<4, 256, 32>, a, blocks, 256, stream);
     default: return (int)hipErrorInvalidValue;
     }
 }
 
+// Maps a runtime (R, TB[, TR]) onto the template instantiation F<R, TB[, TR]>.
+#define TC_FWD_VARIANTS(X) X(2, 32) X(4, 32) X(8, 32) X(2, 64) X(4, 64) X(8, 64)
+#define TC_ADJ_VARIANTS(X) X(2, 32, 4) X(4, 32, 4) X(8, 32, 4) X(2, 64, 4) X(4, 64, 4) X(8, 64, 4)
+
 int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 {
     const int blocks = a.ncol * a.ntile;
-    switch (t.R) {
-    case 2: return launch_grid(k_fwd<2, 256>, a, blocks, 256, stream);
-    case 4: return launch_grid(k_fwd<4, 256>, a, blocks, 256, stream);
-    case 8: return launch_grid(k_fwd<8, 256>, a, blocks, 256, stream);
-    default: return (int)hipErrorInvalidValue;
-    }
+#define X(r, tb) if (t.R == r && t.TB == tb) return launch_grid(k_fwd<r, 256, tb>, a, blocks, 256, stream);
+    TC_FWD_VARIANTS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_adj(const AdjArgs& a, Tile t, void* stream)
 {
     const int blocks = a.ncol * a.ntile;
-    switch (t.R) {
-    case 2: return launch_grid(k_adj<2, 256>, a, blocks, 256, stream);
-    case 4: return launch_grid(k_adj<4, 256>, a, blocks, 256, stream);
-    case 8: return launch_grid(k_adj<8, 256>, a, blocks, 256, stream);
-    default: return (int)hipErrorInvalidValue;
-    }
+#define X(r, tb, tr) \
+    if (t.R == r && t.TB == tb && t.TR == tr) return launch_grid(k_adj<r, 256, tb, tr>, a, blocks, 256, stream);
+    TC_ADJ_VARIANTS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_adj_epilogue(const EpiArgs& e, void* stream)
@@ -839,26 +876,29 @@ int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* cou
                      void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    switch (t.R) {
-    case 2: hipLaunchKernelGGL((k_fwd_queue<2, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    case 4: hipLaunchKernelGGL((k_fwd_queue<4, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    case 8: hipLaunchKernelGGL((k_fwd_queue<8, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    default: return (int)hipErrorInvalidValue;
+#define X(r, tb)                                                                                            \
+    if (t.R == r && t.TB == tb) {                                                                           \
+        hipLaunchKernelGGL((k_fwd_queue<r, 256, tb>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); \
+        return (int)hipGetLastError();                                                                      \
     }
-    return (int)hipGetLastError();
+    TC_FWD_VARIANTS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
                      void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    switch (t.R) {
-    case 2: hipLaunchKernelGGL((k_adj_queue<2, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    case 4: hipLaunchKernelGGL((k_adj_queue<4, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    case 8: hipLaunchKernelGGL((k_adj_queue<8, 256>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); break;
-    default: return (int)hipErrorInvalidValue;
+#define X(r, tb, tr)                                                                                        \
+    if (t.R == r && t.TB == tb && t.TR == tr) {                                                             \
+        hipLaunchKernelGGL((k_adj_queue<r, 256, tb, tr>), dim3(grid), dim3(256), 0, s, dets, items, nitems, \
+                           counter);                                                                        \
+        return (int)hipGetLastError();                                                                      \
     }
-    return (int)hipGetLastError();
+    TC_ADJ_VARIANTS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream)
@@ -872,20 +912,19 @@ int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm
 // Resident workgroups per CU of the persistent kernels (for sizing their grid).
 int queue_occupancy(int op, Tile t, int* blocks_per_cu)
 {
-    hipError_t rc = hipErrorInvalidValue;
     int n = 0;
+    hipError_t rc = hipErrorInvalidValue;
     if (op == 1) {
-        switch (t.R) {
-        case 2: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<2, 256>, 256, 0); break;
-        case 4: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<4, 256>, 256, 0); break;
-        case 8: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<8, 256>, 256, 0); break;
-        }
+#define X(r, tb) \
+        if (t.R == r && t.TB == tb) rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb>, 256, 0);
+        TC_FWD_VARIANTS(X)
+#undef X
     } else if (op == 2) {
-        switch (t.R) {
-        case 2: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<2, 256>, 256, 0); break;
-        case 4: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<4, 256>, 256, 0); break;
-        case 8: rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<8, 256>, 256, 0); break;
-        }
+#define X(r, tb, tr)                           \
+        if (t.R == r && t.TB == tb && t.TR == tr) \
+            rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<r, 256, tb, tr>, 256, 0);
+        TC_ADJ_VARIANTS(X)
+#undef X
     }
     *blocks_per_cu = n;
     return (int)rc;
