@@ -31,11 +31,35 @@ FLOPS_PER_TERM_PAIRED = 6.5
 FLOPS_PER_TERM_UNPAIRED = 9.0
 
 
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over
+# this bench (the kernels' dispatches at lmax 4096), each counter scaled by what it
+# reads for a device-to-device copy of known size in the same run.  Valid only for
+# the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
+MEASURED_TRAFFIC = {
+    "kernel_source_sha256": "207ccca218aaa066c07d995ae5525436a6f6e691cf4aa4c20a250d818b8d6820",
+    "lmax4096": {
+        # FETCH_SIZE KiB x 1024 x 2.000 + WRITE_SIZE KiB x 1024 x 1.000 (2 GiB copy calibration)
+        "k_fwd": int(564556.25 * 1024 * 2.0 + 15208064.0 * 1024),
+        "k_adj": int(5937291.0 * 1024 * 2.0 + 15227844.3125 * 1024),
+    },
+}
+
+
+def hbm_traffic(kernel, workload):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1002_1050_amd", "csrc", "tc_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != MEASURED_TRAFFIC["kernel_source_sha256"]:
+        return None
+    return MEASURED_TRAFFIC.get(workload, {}).get(kernel)
+
+
 def parse():
     p = argparse.ArgumentParser(description=__doc__)
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="lmax4096")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="wall-clock budget of the oracle sample (0 disables)")
@@ -43,6 +67,8 @@ def parse():
     p.add_argument("--batched-reps", type=int, default=3,
                    help="interleaved repetitions of the sixteen-detector batched-vs-plain comparison (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
+    p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
+    p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB' (skips its autotuning)")
     p.add_argument("--copy-calibration-gib", type=float, default=0.0,
                    help="first run one device-to-device copy of this many GiB (a reference kernel of known "
                         "traffic for hardware byte counters)")
@@ -211,16 +237,25 @@ def main():
     torch.cuda.synchronize()
     log("set-up done")
 
-    tiles = {"forward": "built-in", "adjoint": "built-in"}
-    if not args.no_tune:
+    def given(spec):
+        r, tb = (int(v) for v in spec.split(","))
+        return (r, tb, 4)
+
+    tf = given(args.tile_fwd) if args.tile_fwd else None
+    ta = given(args.tile_adj) if args.tile_adj else None
+    if not args.no_tune and (tf is None or ta is None):
         from paper_1002_1050_amd import autotune
-        tf = autotune.tune_plain(B.TC_OP_FWD, w.lmax, w.mbmax, x, alm, blm, reps=1)
-        ta = autotune.tune_plain(B.TC_OP_ADJ, w.lmax, w.mbmax, x, alm, blm, G, reps=1)
-        B.set_tile_ex(B.TC_OP_FWD, *tf)
-        B.set_tile_ex(B.TC_OP_ADJ, *ta)
-        tiles = {"forward": list(tf), "adjoint": list(ta)}
+        if tf is None:
+            tf = autotune.tune_plain(B.TC_OP_FWD, w.lmax, w.mbmax, x, alm, blm, reps=1)
+        if ta is None:
+            ta = autotune.tune_plain(B.TC_OP_ADJ, w.lmax, w.mbmax, x, alm, blm, G, reps=1)
         log(f"autotuned tiles (R, TB, TR): forward {tf}, adjoint {ta}")
         torch.cuda.empty_cache()
+    tf = tf or B.get_tile_ex(B.TC_OP_FWD, w.lmax)
+    ta = ta or B.get_tile_ex(B.TC_OP_ADJ, w.lmax)
+    B.set_tile_ex(B.TC_OP_FWD, *tf)
+    B.set_tile_ex(B.TC_OP_ADJ, *ta)
+    tiles = {"forward": list(tf), "adjoint": list(ta)}
 
     def step():
         B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
@@ -234,6 +269,7 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
     ev = []
+    B.timing_enable(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -249,14 +285,21 @@ def main():
     elapsed = time.perf_counter() - t0
     fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev])) if not args.fwd_only else 0.0
-    log(f"timed {args.steps} steps in {elapsed:.3f} s; forward {fwd_ms:.2f} ms, adjoint {adj_ms:.2f} ms")
+    # HIP events recorded by the library on this stream directly around each recursion kernel
+    k_fwd = B.timing_read(B.TC_OP_FWD, args.steps)
+    k_adj = B.timing_read(B.TC_OP_ADJ, args.steps) if not args.fwd_only else []
+    B.timing_enable(0)
+    kfwd_ms = float(np.mean(k_fwd))
+    kadj_ms = float(np.mean(k_adj)) if k_adj else 0.0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; forward {fwd_ms:.2f} ms, adjoint {adj_ms:.2f} ms; "
+        f"kernels: k_fwd {kfwd_ms:.2f} ms, k_adj {kadj_ms:.2f} ms")
 
     passes = 1 if args.fwd_only else 2
     ms_per_step = elapsed / args.steps * 1e3
     value = passes * terms / (elapsed / args.steps)
     paired = bool(np.all(x[::-1][: w.nring // 2] == -x[: w.nring // 2]))
     fpt = FLOPS_PER_TERM_PAIRED if paired else FLOPS_PER_TERM_UNPAIRED
-    dom_name, dom_ms = ("totalconv_adj (k_adj + epilogues)", adj_ms) if adj_ms > fwd_ms else ("totalconv_fwd (k_fwd)", fwd_ms)
+    dom_name, dom_ms = ("k_adj", kadj_ms) if kadj_ms > kfwd_ms else ("k_fwd", kfwd_ms)
     achieved = fpt * terms / (dom_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu",
@@ -265,10 +308,15 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": hbm_traffic(dom_name, w.name),
         "flops_per_term": fpt,
         "terms_per_launch": terms,
         "launch_ms": round(dom_ms, 3),
+        "launch_ms_per_step": [round(v, 3) for v in (k_adj if dom_name == "k_adj" else k_fwd)],
+        "other_kernel": {"name": "k_fwd" if dom_name == "k_adj" else "k_adj",
+                         "launch_ms": round(kfwd_ms if dom_name == "k_adj" else kadj_ms, 3),
+                         "frac": round(fpt * terms / ((kfwd_ms if dom_name == "k_adj" else kadj_ms) or float("inf"))
+                                       / 1e9 / FP64_VECTOR_PEAK_TFLOPS, 4)},
     }
     result = {
         "metric": "(l,mb,msky,beta) convolution terms/s, forward + adjoint",

@@ -192,6 +192,27 @@ int tc_plan_tile(void* plan);
 /* Release the plan (synchronises with its last launch first).  NULL is ignored. */
 int tc_plan_destroy(void* plan);
 
+/*
+ * Kernel timing (diagnostics, not in the paper).  tc_timing_enable(n), n >= 1,
+ * creates n pairs of HIP timing events per operation on the current device;
+ * from then on every wigner_d_rings / totalconv_fwd / totalconv_adj call
+ * records one pair on its own stream, directly before and after its recursion
+ * kernel (for the adjoint: without the two short epilogue kernels that finish
+ * the gradients), reusing the pairs cyclically.  n = 0 releases the events and
+ * stops the recording.  Calls must then run on streams of that device.
+ * Returns TC_OK, TC_EINVAL for n < 0 or n > 65536, TC_EHIP if event creation
+ * fails.  Not thread-safe: enable, read and the timed calls belong to one thread.
+ */
+int tc_timing_enable(int n);
+
+/*
+ * Waits for the pairs of the last k = min(n, recorded, capacity) calls of `op`
+ * and writes their kernel durations in milliseconds to ms[0..k-1] (host),
+ * oldest first.  Returns k (0 if timing is off or nothing was recorded), or a
+ * negative TC_E* code.
+ */
+int tc_timing_read(int op, float* ms, int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,10 @@ def lib():
             L.tc_plan_device_bytes.argtypes = [P]
             L.tc_plan_tile.restype = I
             L.tc_plan_tile.argtypes = [P]
+            L.tc_timing_enable.restype = I
+            L.tc_timing_enable.argtypes = [I]
+            L.tc_timing_read.restype = I
+            L.tc_timing_read.argtypes = [I, ctypes.POINTER(ctypes.c_float), I]
             _lib = L
     return _lib
 
@@ -229,6 +233,20 @@ def get_tile_ex(op: int, lmax: int):
     R, TB, TR = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check("tc_get_tile_ex", lib().tc_get_tile_ex(op, lmax, ctypes.byref(R), ctypes.byref(TB), ctypes.byref(TR)))
     return R.value, TB.value, TR.value
+
+
+def timing_enable(n: int):
+    """Record HIP events around the recursion kernel of the next calls (n pairs per op; 0 = off)."""
+    _check("tc_timing_enable", lib().tc_timing_enable(n))
+
+
+def timing_read(op: int, n: int):
+    """Kernel durations (ms) of the last n recorded calls of `op`, oldest first."""
+    buf = (ctypes.c_float * max(n, 1))()
+    k = lib().tc_timing_read(op, buf, n)
+    if k < 0:
+        raise TotalConvError("tc_timing_read", k, last_error())
+    return [float(buf[i]) for i in range(k)]
 
 
 class Plan:

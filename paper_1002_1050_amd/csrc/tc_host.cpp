@@ -76,6 +76,42 @@ tc::Tile default_tile(int op, int lmax)
     return t;
 }
 
+// ------------------------------------------------------------ kernel timing
+
+// Event pairs recorded around the recursion kernel of each call (tc_timing_*).
+struct KernelTiming {
+    int cap = 0;
+    std::vector<hipEvent_t> start[3], stop[3];
+    long long recorded[3] = {0, 0, 0};
+};
+KernelTiming g_timing;
+
+void timing_release()
+{
+    for (int op = 0; op < 3; ++op) {
+        for (hipEvent_t e : g_timing.start[op]) if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : g_timing.stop[op]) if (e) (void)hipEventDestroy(e);
+        g_timing.start[op].clear();
+        g_timing.stop[op].clear();
+        g_timing.recorded[op] = 0;
+    }
+    g_timing.cap = 0;
+}
+
+// Launch `launch` between the op's next event pair (plain launch when timing is off).
+template <class F>
+int timed_launch(int op, void* stream, F launch)
+{
+    if (!g_timing.cap) return launch();
+    const int i = (int)(g_timing.recorded[op] % g_timing.cap);
+    int rc = (int)hipEventRecord(g_timing.start[op][i], (hipStream_t)stream);
+    if (rc) return rc;
+    if ((rc = launch())) return rc;
+    if ((rc = (int)hipEventRecord(g_timing.stop[op][i], (hipStream_t)stream))) return rc;
+    ++g_timing.recorded[op];
+    return 0;
+}
+
 // ------------------------------------------------------------- table layout
 
 struct Layout {
@@ -296,6 +332,43 @@ int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR)
 
 int tc_abi_version(void) { return 1; }
 
+int tc_timing_enable(int n)
+{
+    if (n < 0 || n > 65536) return fail(TC_EINVAL, "tc_timing_enable: n = %d outside [0, 65536]", n);
+    timing_release();
+    if (n == 0) return TC_OK;
+    for (int op = 0; op < 3; ++op) {
+        g_timing.start[op].assign(n, nullptr);
+        g_timing.stop[op].assign(n, nullptr);
+        for (int i = 0; i < n; ++i) {
+            int rc = (int)hipEventCreate(&g_timing.start[op][i]);
+            if (!rc) rc = (int)hipEventCreate(&g_timing.stop[op][i]);
+            if (rc) {
+                timing_release();
+                return hip_fail(rc, "tc_timing_enable: hipEventCreate");
+            }
+        }
+    }
+    g_timing.cap = n;
+    return TC_OK;
+}
+
+int tc_timing_read(int op, float* ms, int n)
+{
+    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_timing_read: unknown op %d", op);
+    if (n < 0 || (n > 0 && !ms)) return fail(TC_EINVAL, "tc_timing_read: bad output buffer");
+    if (!g_timing.cap) return 0;
+    const long long rec = g_timing.recorded[op];
+    const int k = (int)std::min<long long>(std::min<long long>(n, rec), g_timing.cap);
+    for (int t = 0; t < k; ++t) {
+        const int i = (int)((rec - k + t) % g_timing.cap);
+        int rc = (int)hipEventSynchronize(g_timing.stop[op][i]);
+        if (!rc) rc = (int)hipEventElapsedTime(&ms[t], g_timing.start[op][i], g_timing.stop[op][i]);
+        if (rc) return hip_fail(rc, "tc_timing_read");
+    }
+    return k;
+}
+
 size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring)
 {
     if (nring < 1 || lmax < 0 || lmax > TC_LMAX_LIMIT) return 0;
@@ -343,7 +416,7 @@ int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nrin
     a.ring = ring_ptrs(workspace, L, nring);
     a.col = col_ptrs(workspace, L);
     a.d = d;
-    rc = tc::launch_wigner(a, t, stream);
+    rc = timed_launch(TC_OP_WIGNER, stream, [&] { return tc::launch_wigner(a, t, stream); });
     return rc ? hip_fail(rc, "wigner_d_rings launch") : TC_OK;
 }
 
@@ -372,7 +445,7 @@ int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta, const d
     a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
     a.col = col_ptrs(workspace, L);
     a.alm = alm; a.blm = blm; a.C = C;
-    rc = tc::launch_fwd(a, t, stream);
+    rc = timed_launch(TC_OP_FWD, stream, [&] { return tc::launch_fwd(a, t, stream); });
     return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
 }
 
@@ -406,7 +479,7 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const d
     a.U = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
     a.V = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
     a.P = L.P;
-    rc = tc::launch_adj(a, t, stream);
+    rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
     if (rc) return hip_fail(rc, "totalconv_adj launch");
     tc::EpiArgs e{};
     e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax;

@@ -106,3 +106,13 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         B.lib()
+
+
+def test_timing_arguments_checked_on_host(L):
+    buf = (ctypes.c_float * 4)()
+    assert L.tc_timing_enable(-1) == -1
+    assert L.tc_timing_enable(65537) == -1
+    assert L.tc_timing_read(3, buf, 4) == -1
+    assert L.tc_timing_read(1, None, 4) == -1
+    assert L.tc_timing_read(1, buf, 4) == 0          # timing off: nothing recorded
+    assert L.tc_timing_enable(0) == 0
