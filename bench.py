@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--fwd-only", action="store_true", help="time the forward alone")
     p.add_argument("--batched-reps", type=int, default=3,
                    help="interleaved repetitions of the sixteen-detector batched-vs-plain comparison (0 skips)")
+    p.add_argument("--pol-reps", type=int, default=2,
+                   help="timed repetitions of the polarised forward (three pairs, separate and summed; 0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
     p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB' (skips its autotuning)")
@@ -194,6 +196,45 @@ def batched_compare(reps, tune):
         "reps": reps,
     }
     plan.close()
+    return res
+
+
+def polarised_compare(w, x, alm, blm, reps, tune):
+    """Polarised forward on the same workload: temperature, gradient and curl pairs (three
+    seeded skies, three beams) sharing one recursion, as three outputs and as their sum.
+    Terms count each pair's (l, mb, msky, beta) terms."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import synthetic as S
+    dev = alm.device
+    alms = [alm] + [torch.from_numpy(S.sky_alm(w.lmax, w.sky_seed + 1 + p)).to(dev) for p in range(2)]
+    blms = [blm] + [torch.from_numpy(S.random_beam(w.lmax, w.mbmax, 77 + p)).to(dev) for p in range(2)]
+    tile = B.get_tile_ex(B.TC_OP_FWD_POL, w.lmax)
+    if tune:
+        from paper_1002_1050_amd import autotune
+        tile = autotune.tune_plain(B.TC_OP_FWD_POL, w.lmax, w.mbmax, x, alms, blms, reps=1)
+    B.set_tile_ex(B.TC_OP_FWD_POL, *tile)
+    terms = 3 * w.terms()
+    res = {"workload": f"polarised forward, three (sky, beam) pairs, lmax={w.lmax}, mbmax={w.mbmax}, "
+                       f"{w.nring} rings", "terms": terms, "tile_R_TB": list(tile[:2])}
+    for name, mode in (("separate", B.TC_POL_SEPARATE), ("summed", B.TC_POL_SUM)):
+        outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, mode)   # warm-up
+        del outs
+        torch.cuda.synchronize()
+        B.timing_enable(reps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, mode)
+            del outs
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        kms = float(np.mean(B.timing_read(B.TC_OP_FWD_POL, reps)))
+        B.timing_enable(0)
+        res[name] = {"kernel_ms": round(kms, 3), "call_ms": round(wall * 1e3, 3),
+                     "terms_per_s": terms / (kms * 1e-3)}
+        log(f"  polarised {name}: kernel {kms:.1f} ms, {terms / (kms * 1e-3):.3e} terms/s")
+        torch.cuda.empty_cache()
+    B.set_tile_ex(B.TC_OP_FWD_POL, 0, 0, 0)
     return res
 
 
@@ -357,6 +398,12 @@ def main():
         del Gc
     B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
+    if args.pol_reps > 0:
+        del C
+        torch.cuda.empty_cache()
+        log("polarised forward")
+        result["polarised"] = polarised_compare(w, x, alm, blm, args.pol_reps, not args.no_tune)
+        C = None
     if args.batched_reps > 0:
         del C, G
         torch.cuda.empty_cache()

@@ -56,6 +56,10 @@ extern "C" {
 #define TC_OP_WIGNER 0
 #define TC_OP_FWD 1
 #define TC_OP_ADJ 2
+#define TC_OP_FWD_POL 3       /* tiles / workspace of totalconv_fwd_pol */
+
+#define TC_POL_SEPARATE 0     /* polarised: one output per (sky, beam) pair */
+#define TC_POL_SUM 1          /* polarised: one output, the sum over the pairs */
 
 #define TC_LMAX_LIMIT 16384
 
@@ -68,7 +72,8 @@ int tc_abi_version(void);
 /*
  * Device workspace, in bytes, that an entry point needs.
  *   op = TC_OP_WIGNER: `mbmax` is the number of (mb, msky) pairs;
- *   op = TC_OP_FWD / TC_OP_ADJ: the arguments of totalconv_fwd / totalconv_adj.
+ *   op = TC_OP_FWD / TC_OP_ADJ / TC_OP_FWD_POL: the arguments of totalconv_fwd /
+ *   totalconv_adj (and totalconv_adj_pol) / totalconv_fwd_pol.
  * Returns 0 for invalid arguments.
  */
 size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring);
@@ -130,10 +135,47 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
                   void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Polarised total convolution (footnote of Sec. 4.1: eq. convdef evaluated for
+ * the additional gradient and curl pairs (b^G, s^G), (b^C, s^C) beside the
+ * temperature pair).  The npair (1..3) pairs share one recursion.
+ *   alm, blm     (host) arrays of npair device pointers, each laid out as in
+ *                totalconv_fwd (pair p: s^p and b^p)
+ *   mode         TC_POL_SEPARATE: C[p] = C^p, the convolution of pair p
+ *                (npair outputs);
+ *                TC_POL_SUM: C[0] = sum_p C^p, the polarised detector's
+ *                coefficients (one output)
+ *   C            (host) array of device pointers to the outputs, each laid out
+ *                as C of totalconv_fwd
+ *   workspace    at least totalconv_workspace_bytes(TC_OP_FWD_POL, lmax, mbmax, nring) bytes
+ * Each output equals, up to rounding order, the sum of totalconv_fwd over the
+ * pairs it covers.  TC_EINVAL for npair outside [1, 3], an unknown mode or a
+ * NULL pointer among the used entries.
+ */
+int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+                      const double* const* alm, const double* const* blm, int mode,
+                      double* const* C, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of totalconv_fwd_pol.  Cbar: (host) array of device pointers to the
+ * cotangents of the outputs (npair for TC_POL_SEPARATE, 1 for TC_POL_SUM).
+ * alm_bar, blm_bar: (host) arrays of npair device pointers (entries may be
+ * NULL; either array may be NULL) receiving the gradients of pair p, as
+ * totalconv_adj gives them for that pair's sky, beam and cotangent.  In
+ * TC_POL_SUM mode the pairs share one reduction over the rings; in
+ * TC_POL_SEPARATE mode the cotangents are reduced one after the other.
+ *   workspace    at least totalconv_workspace_bytes(TC_OP_ADJ, lmax, mbmax, nring) bytes
+ */
+int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+                      const double* const* alm, const double* const* blm, int mode,
+                      const double* const* Cbar, double* const* alm_bar, double* const* blm_bar,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Tile selection for later calls in this process (not in the paper; a tuning
  * knob of this implementation).  Each lane walks R chains; a workgroup covers
- * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8})
- * or TC_OP_WIGNER (R in {1, 4}); R = 0 restores the built-in choice.  Affects
+ * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8}),
+ * TC_OP_FWD_POL (R in {2, 4}) or TC_OP_WIGNER (R in {1, 4}); R = 0 restores the
+ * built-in choice.  Affects
  * the workspace sizes reported afterwards.  Returns TC_EINVAL for other values.
  * Not synchronised: set it from the thread that issues the calls.
  */
@@ -195,10 +237,12 @@ int tc_plan_destroy(void* plan);
 /*
  * Kernel timing (diagnostics, not in the paper).  tc_timing_enable(n), n >= 1,
  * creates n pairs of HIP timing events per operation on the current device;
- * from then on every wigner_d_rings / totalconv_fwd / totalconv_adj call
- * records one pair on its own stream, directly before and after its recursion
- * kernel (for the adjoint: without the two short epilogue kernels that finish
- * the gradients), reusing the pairs cyclically.  n = 0 releases the events and
+ * from then on every wigner_d_rings / totalconv_fwd / totalconv_adj /
+ * totalconv_fwd_pol call records one pair (under op TC_OP_WIGNER, TC_OP_FWD,
+ * TC_OP_ADJ, TC_OP_FWD_POL) on its own stream, directly before and after its
+ * recursion kernel (for the adjoint: without the two short epilogue kernels
+ * that finish the gradients; totalconv_adj_pol records one TC_OP_ADJ pair per
+ * cotangent), reusing the pairs cyclically.  n = 0 releases the events and
  * stops the recording.  Calls must then run on streams of that device.
  * Returns TC_OK, TC_EINVAL for n < 0 or n > 65536, TC_EHIP if event creation
  * fails.  Not thread-safe: enable, read and the timed calls belong to one thread.

@@ -201,3 +201,34 @@ def totalconv_adj(lmax: int, mbmax: int, xring, alm, blm, Gbar, nthreads: int = 
     bbim = (sim_ * ure - sre_ * uim).sum(axis=1)
     beam_bar = bbre.astype(np.float64) + 1j * bbim.astype(np.float64)
     return sky_bar, beam_bar
+
+
+def totalconv_fwd_pol(lmax: int, mbmax: int, xring, alms, blms, summed: bool = False,
+                      nthreads: int = 0):
+    """Polarised total convolution (footnote of Sec. 4.1): eq. convdef evaluated for each
+    (sky, beam) pair -- temperature, gradient, curl.  Returns the list of per-pair C, or
+    (summed) a one-element list holding their sum, the polarised detector's coefficients."""
+    if not 1 <= len(alms) <= 3 or len(blms) != len(alms):
+        raise ValueError("1 to 3 (alm, blm) pairs")
+    outs = [totalconv_fwd(lmax, mbmax, xring, a, b, nthreads=nthreads) for a, b in zip(alms, blms)]
+    if summed:
+        total = outs[0].copy()
+        for c in outs[1:]:
+            total += c
+        return [total]
+    return outs
+
+
+def totalconv_adj_pol(lmax: int, mbmax: int, xring, alms, blms, Gbars, summed: bool = False,
+                      nthreads: int = 0):
+    """Gradients of totalconv_fwd_pol: pair p gets the scalar adjoint of its own sky and beam
+    for its cotangent (summed: the one cotangent of the summed output).  Returns
+    ([sky_bar per pair], [beam_bar per pair])."""
+    if len(Gbars) != (1 if summed else len(alms)):
+        raise ValueError("one cotangent per output")
+    sky, beam = [], []
+    for p, (a, b) in enumerate(zip(alms, blms)):
+        sb, bb = totalconv_adj(lmax, mbmax, xring, a, b, Gbars[0 if summed else p], nthreads=nthreads)
+        sky.append(sb)
+        beam.append(bb)
+    return sky, beam

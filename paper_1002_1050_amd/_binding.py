@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtotalconv.so")
 
-TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ = 0, 1, 2
+TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL = 0, 1, 2, 3
+TC_POL_SEPARATE, TC_POL_SUM = 0, 1
 TC_LMAX_LIMIT = 16384
 
 _lib = None
@@ -80,6 +81,11 @@ def lib():
             L.tc_plan_device_bytes.argtypes = [P]
             L.tc_plan_tile.restype = I
             L.tc_plan_tile.argtypes = [P]
+            PP = ctypes.POINTER(P)
+            L.totalconv_fwd_pol.restype = I
+            L.totalconv_fwd_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, P, S, P]
+            L.totalconv_adj_pol.restype = I
+            L.totalconv_adj_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, PP, PP, P, S, P]
             L.tc_timing_enable.restype = I
             L.tc_timing_enable.argtypes = [I]
             L.tc_timing_read.restype = I
@@ -213,6 +219,69 @@ def totalconv_adj(lmax: int, mbmax: int, cosbeta, alm, blm, Cbar, want_alm=True,
                              _dptr(alm_bar), _dptr(blm_bar), _dptr(ws), ws.numel(), stream)
     _check("totalconv_adj", rc)
     return alm_bar, blm_bar
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * max(len(ts), 1))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr() if t is not None else None
+    return arr
+
+
+def _pol_inputs(torch, lmax, mbmax, alms, blms):
+    alms, blms = list(alms), list(blms)
+    if not 1 <= len(alms) <= 3 or len(blms) != len(alms):
+        raise ValueError("1 to 3 (alm, blm) pairs are required")
+    for i, (a, b) in enumerate(zip(alms, blms)):
+        _require_device(a, f"alms[{i}]", torch.complex128)
+        _require_device(b, f"blms[{i}]", torch.complex128)
+        if a.numel() != (lmax + 1) * (lmax + 2) // 2 or b.numel() != (2 * mbmax + 1) * (lmax + 1):
+            raise ValueError(f"pair {i}: alm / blm sizes do not match lmax / mbmax")
+    return alms, blms
+
+
+def totalconv_fwd_pol(lmax: int, mbmax: int, cosbeta, alms, blms, mode=TC_POL_SEPARATE):
+    """Polarised convolution of 1-3 (alm, blm) pairs sharing one recursion.  Returns a list of
+    one C per pair (TC_POL_SEPARATE) or a list holding the summed C (TC_POL_SUM)."""
+    import torch
+    alms, blms = _pol_inputs(torch, lmax, mbmax, alms, blms)
+    device = alms[0].device
+    x = _host(cosbeta, np.float64)
+    nout = 1 if mode == TC_POL_SUM else len(alms)
+    outs = [torch.empty((2 * mbmax + 1, lmax + 1, x.size), dtype=torch.complex128, device=device)
+            for _ in range(nout)]
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, workspace_bytes(TC_OP_FWD_POL, lmax, mbmax, x))
+    rc = lib().totalconv_fwd_pol(lmax, mbmax, x.size, _hptr(x), len(alms), _ptr_array(alms), _ptr_array(blms),
+                                 mode, _ptr_array(outs), _dptr(ws), ws.numel(), stream)
+    _check("totalconv_fwd_pol", rc)
+    return outs
+
+
+def totalconv_adj_pol(lmax: int, mbmax: int, cosbeta, alms, blms, Cbars, mode=TC_POL_SEPARATE,
+                      want_alm=True, want_blm=True):
+    """Gradients ([alm_bar per pair], [blm_bar per pair]) of totalconv_fwd_pol for the cotangents
+    Cbars (one per output); entries are None when not requested."""
+    import torch
+    alms, blms = _pol_inputs(torch, lmax, mbmax, alms, blms)
+    Cbars = list(Cbars)
+    x = _host(cosbeta, np.float64)
+    if len(Cbars) != (1 if mode == TC_POL_SUM else len(alms)):
+        raise ValueError("one cotangent per output is required")
+    for i, g in enumerate(Cbars):
+        _require_device(g, f"Cbars[{i}]", torch.complex128)
+        if g.numel() != (2 * mbmax + 1) * (lmax + 1) * x.size:
+            raise ValueError("Cbar size does not match (2*mbmax+1, lmax+1, nring)")
+    device = alms[0].device
+    abar = [torch.empty_like(a) if want_alm else None for a in alms]
+    bbar = [torch.empty_like(b) if want_blm else None for b in blms]
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, workspace_bytes(TC_OP_ADJ, lmax, mbmax, x))
+    rc = lib().totalconv_adj_pol(lmax, mbmax, x.size, _hptr(x), len(alms), _ptr_array(alms), _ptr_array(blms),
+                                 mode, _ptr_array(Cbars), _ptr_array(abar) if want_alm else None,
+                                 _ptr_array(bbar) if want_blm else None, _dptr(ws), ws.numel(), stream)
+    _check("totalconv_adj_pol", rc)
+    return abar, bbar
 
 
 def set_tile(op: int, R: int):

@@ -41,3 +41,40 @@ class TotalConv(torch.autograd.Function):
 
 def totalconv(alm, blm, cosbeta, lmax: int, mbmax: int):
     return TotalConv.apply(alm, blm, cosbeta, lmax, mbmax)
+
+
+class TotalConvPol(torch.autograd.Function):
+    """Polarised form: TotalConvPol.apply(mode, cosbeta, lmax, mbmax, alm_0, .., alm_{n-1},
+    blm_0, .., blm_{n-1}) for n = 1..3 (temperature, gradient, curl) pairs; returns one C per
+    pair (TC_POL_SEPARATE) or the one summed C (TC_POL_SUM), as a tuple."""
+
+    @staticmethod
+    def forward(ctx, mode, cosbeta, lmax, mbmax, *tensors):
+        n = len(tensors) // 2
+        if len(tensors) != 2 * n or not 1 <= n <= 3:
+            raise ValueError("pass 1 to 3 sky tensors followed by as many beam tensors")
+        x = np.ascontiguousarray(cosbeta, dtype=np.float64)
+        alms = [t.detach().contiguous() for t in tensors[:n]]
+        blms = [t.detach().contiguous() for t in tensors[n:]]
+        outs = _binding.totalconv_fwd_pol(lmax, mbmax, x, alms, blms, mode)
+        ctx.save_for_backward(*tensors)
+        ctx.x, ctx.lmax, ctx.mbmax, ctx.mode, ctx.n = x, lmax, mbmax, mode, n
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        tensors = ctx.saved_tensors
+        n = ctx.n
+        want_a = any(ctx.needs_input_grad[4:4 + n])
+        want_b = any(ctx.needs_input_grad[4 + n:4 + 2 * n])
+        none = (None,) * 4
+        if not (want_a or want_b):
+            return none + (None,) * (2 * n)
+        shape = (2 * ctx.mbmax + 1, ctx.lmax + 1, ctx.x.size)
+        cot = [g if g is not None else torch.zeros(shape, dtype=torch.complex128, device=tensors[0].device)
+               for g in grads]
+        ga, gb = _binding.totalconv_adj_pol(ctx.lmax, ctx.mbmax, ctx.x, [t.detach().contiguous() for t in tensors[:n]],
+                                            [t.detach().contiguous() for t in tensors[n:]],
+                                            [g.contiguous() for g in cot], ctx.mode,
+                                            want_alm=want_a, want_blm=want_b)
+        return none + tuple(ga) + tuple(gb)

@@ -19,6 +19,7 @@ from . import _binding as B
 CANDIDATES = {
     B.TC_OP_FWD: [(r, tb, 4) for tb in (32, 64) for r in (2, 4, 8)],
     B.TC_OP_ADJ: [(r, tb, 4) for tb in (32, 64) for r in (2, 4, 8)],
+    B.TC_OP_FWD_POL: [(r, tb, 4) for tb in (32, 64) for r in (2, 4)],
 }
 
 
@@ -71,8 +72,10 @@ def _gpu_name():
 
 
 def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=True):
-    """Best (R, TB, TR) for a plain totalconv_fwd / totalconv_adj call of this shape."""
-    key = f"plain:{op}:{lmax}:{mbmax}:{len(cosbeta)}:{_gpu_name()}"
+    """Best (R, TB, TR) for a plain totalconv_fwd / totalconv_adj / totalconv_fwd_pol call of this
+    shape (for the polarised forward, alm and blm are the lists of pairs)."""
+    npair = len(alm) if op == B.TC_OP_FWD_POL else 1
+    key = f"plain:{op}:{lmax}:{mbmax}:{len(cosbeta)}:{npair}:{_gpu_name()}"
     cache = _load() if use_cache else {}
     if key in cache:
         return tuple(cache[key]["tile"])
@@ -83,6 +86,8 @@ def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=
             B.set_tile_ex(op, *t)
             if op == B.TC_OP_FWD:
                 times[t] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
+            elif op == B.TC_OP_FWD_POL:   # alm, blm: lists of pairs; separate outputs
+                times[t] = _time(lambda: B.totalconv_fwd_pol(lmax, mbmax, cosbeta, alm, blm), reps)
             else:
                 B.workspace_cache.clear()
                 times[t] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)

@@ -58,7 +58,8 @@ void split_dd(ld v, double& hi, double& lo)
 
 // ---------------------------------------------------------------- tile choice
 
-tc::Tile g_tile_override[3] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // tc_set_tile_ex; 0 = built-in
+constexpr int kNumOps = 4;   // TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL
+tc::Tile g_tile_override[kNumOps] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // 0 = built-in
 
 tc::Tile default_tile(int op, int lmax)
 {
@@ -67,7 +68,8 @@ tc::Tile default_tile(int op, int lmax)
     tc::Tile t{4, 256, 32, 4};
     if (op == TC_OP_FWD) t = lmax >= 256 ? tc::Tile{4, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
     if (op == TC_OP_ADJ) t = lmax >= 256 ? tc::Tile{8, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
-    if (op >= 0 && op < 3) {
+    if (op == TC_OP_FWD_POL) t = lmax >= 256 ? tc::Tile{4, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
+    if (op >= 0 && op < kNumOps) {
         const tc::Tile& o = g_tile_override[op];
         if (o.R > 0) t.R = o.R;
         if (o.TB > 0) t.TB = o.TB;
@@ -81,14 +83,14 @@ tc::Tile default_tile(int op, int lmax)
 // Event pairs recorded around the recursion kernel of each call (tc_timing_*).
 struct KernelTiming {
     int cap = 0;
-    std::vector<hipEvent_t> start[3], stop[3];
-    long long recorded[3] = {0, 0, 0};
+    std::vector<hipEvent_t> start[kNumOps], stop[kNumOps];
+    long long recorded[kNumOps] = {0, 0, 0, 0};
 };
 KernelTiming g_timing;
 
 void timing_release()
 {
-    for (int op = 0; op < 3; ++op) {
+    for (int op = 0; op < kNumOps; ++op) {
         for (hipEvent_t e : g_timing.start[op]) if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : g_timing.stop[op]) if (e) (void)hipEventDestroy(e);
         g_timing.start[op].clear();
@@ -288,6 +290,105 @@ int check_grid(const Layout& L)
     return TC_OK;
 }
 
+// Forward for npair (sky, beam) pairs: one output per pair, or (sum) one output.
+int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+             const double* const* blm, int sum, double* const* C, void* workspace, size_t ws_bytes, void* stream)
+{
+    int rc = check_sizes(lmax, mbmax);
+    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
+    const int nout = sum ? 1 : npair;
+    for (int p = 0; p < npair; ++p) {
+        if (!alm[p] || !blm[p]) return fail(TC_EINVAL, "alm or blm of pair %d is NULL", p);
+        if (!aligned16(alm[p]) || !aligned16(blm[p])) return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+    }
+    for (int c = 0; c < nout; ++c) {
+        if (!C[c]) return fail(TC_EINVAL, "C of output %d is NULL", c);
+        if (!aligned16(C[c])) return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+    }
+    const tc::Tile t = default_tile(op, lmax);
+    const Layout L = make_layout(op, lmax, mbmax, nring, cosbeta, t);
+    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
+    std::vector<char> img(L.tables_end, 0);
+    build_rings(nring, cosbeta, img, L);
+    build_slots(nring, cosbeta, img, L);
+    build_columns(lmax, mbmax, img, L);
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::FwdArgs a{};
+    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
+    a.sky_lmax = lmax;
+    a.skip_exp = 100;
+    a.ring = ring_ptrs(workspace, L, nring);
+    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
+    a.col = col_ptrs(workspace, L);
+    a.npair = npair;
+    a.sum = sum;
+    for (int p = 0; p < npair; ++p) { a.alm[p] = alm[p]; a.blm[p] = blm[p]; }
+    for (int c = 0; c < nout; ++c) a.C[c] = C[c];
+    rc = timed_launch(op, stream, [&] { return tc::launch_fwd(a, t, stream); });
+    return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
+}
+
+// Adjoint for npair pairs.  Summed outputs share one cotangent, hence one u per
+// column and l; separate outputs have one cotangent each, reduced one after the other.
+int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+             const double* const* blm, int sum, const double* const* Cbar, double* const* alm_bar,
+             double* const* blm_bar, void* workspace, size_t ws_bytes, void* stream)
+{
+    int rc = check_sizes(lmax, mbmax);
+    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
+    const int ncot = sum ? 1 : npair;
+    bool any = false;
+    for (int p = 0; p < npair; ++p) {
+        double* ab = alm_bar ? alm_bar[p] : nullptr;
+        double* bb = blm_bar ? blm_bar[p] : nullptr;
+        if (!alm[p] || !blm[p]) return fail(TC_EINVAL, "alm or blm of pair %d is NULL", p);
+        if (!aligned16(alm[p]) || !aligned16(blm[p]) || (ab && !aligned16(ab)) || (bb && !aligned16(bb)))
+            return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+        any |= (ab != nullptr) || (bb != nullptr);
+    }
+    for (int k = 0; k < ncot; ++k) {
+        if (!Cbar[k]) return fail(TC_EINVAL, "Cbar of output %d is NULL", k);
+        if (!aligned16(Cbar[k])) return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
+    }
+    if (!any) return TC_OK;   // nothing requested
+    const tc::Tile t = default_tile(TC_OP_ADJ, lmax);
+    const Layout L = make_layout(TC_OP_ADJ, lmax, mbmax, nring, cosbeta, t);
+    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
+    std::vector<char> img(L.tables_end, 0);
+    build_rings(nring, cosbeta, img, L);
+    build_slots(nring, cosbeta, img, L);
+    build_columns(lmax, mbmax, img, L);
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::AdjArgs a{};
+    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
+    a.skip_exp = 100;
+    a.ring = ring_ptrs(workspace, L, nring);
+    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
+    a.col = col_ptrs(workspace, L);
+    a.U = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
+    a.V = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
+    a.P = L.P;
+    for (int k = 0; k < ncot; ++k) {
+        const int p0 = sum ? 0 : k, p1 = sum ? npair : k + 1;   // pairs served by cotangent k
+        bool need = false;
+        for (int p = p0; p < p1; ++p)
+            need |= (alm_bar && alm_bar[p]) || (blm_bar && blm_bar[p]);
+        if (!need) continue;
+        a.Cbar = Cbar[k];
+        rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
+        if (rc) return hip_fail(rc, "totalconv_adj launch");
+        for (int p = p0; p < p1; ++p) {
+            tc::EpiArgs e{};
+            e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax;
+            e.U = a.U; e.V = a.V; e.alm = alm[p]; e.blm = blm[p];
+            e.alm_bar = alm_bar ? alm_bar[p] : nullptr;
+            e.blm_bar = blm_bar ? blm_bar[p] : nullptr;
+            if ((rc = tc::launch_adj_epilogue(e, stream))) return hip_fail(rc, "totalconv_adj epilogue launch");
+        }
+    }
+    return TC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -296,7 +397,7 @@ const char* tc_last_error(void) { return g_error.c_str(); }
 
 int tc_set_tile_ex(int op, int R, int TB, int TR)
 {
-    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
+    if (op < 0 || op >= kNumOps) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
     if (R < 0 || TB < 0 || TR < 0) return fail(TC_EINVAL, "tc_set_tile: negative tile parameter");
     const tc::Tile o = g_tile_override[op];
     g_tile_override[op] = tc::Tile{R, 256, TB, TR};
@@ -309,20 +410,20 @@ int tc_set_tile_ex(int op, int R, int TB, int TR)
 
 int tc_set_tile(int op, int R)
 {
-    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
+    if (op < 0 || op >= kNumOps) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
     const tc::Tile o = g_tile_override[op];
     return tc_set_tile_ex(op, R, o.TB, o.TR);
 }
 
 int tc_get_tile(int op, int lmax)
 {
-    if (op < 0 || op > 2) return 0;
+    if (op < 0 || op >= kNumOps) return 0;
     return default_tile(op, lmax).R;
 }
 
 int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR)
 {
-    if (op < 0 || op > 2 || !R || !TB || !TR) return fail(TC_EINVAL, "tc_get_tile_ex: bad arguments");
+    if (op < 0 || op >= kNumOps || !R || !TB || !TR) return fail(TC_EINVAL, "tc_get_tile_ex: bad arguments");
     const tc::Tile t = default_tile(op, lmax);
     *R = t.R;
     *TB = t.TB;
@@ -337,7 +438,7 @@ int tc_timing_enable(int n)
     if (n < 0 || n > 65536) return fail(TC_EINVAL, "tc_timing_enable: n = %d outside [0, 65536]", n);
     timing_release();
     if (n == 0) return TC_OK;
-    for (int op = 0; op < 3; ++op) {
+    for (int op = 0; op < kNumOps; ++op) {
         g_timing.start[op].assign(n, nullptr);
         g_timing.stop[op].assign(n, nullptr);
         for (int i = 0; i < n; ++i) {
@@ -355,7 +456,7 @@ int tc_timing_enable(int n)
 
 int tc_timing_read(int op, float* ms, int n)
 {
-    if (op < 0 || op > 2) return fail(TC_EINVAL, "tc_timing_read: unknown op %d", op);
+    if (op < 0 || op >= kNumOps) return fail(TC_EINVAL, "tc_timing_read: unknown op %d", op);
     if (n < 0 || (n > 0 && !ms)) return fail(TC_EINVAL, "tc_timing_read: bad output buffer");
     if (!g_timing.cap) return 0;
     const long long rec = g_timing.recorded[op];
@@ -374,7 +475,7 @@ size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring)
     if (nring < 1 || lmax < 0 || lmax > TC_LMAX_LIMIT) return 0;
     if (op == TC_OP_WIGNER) {
         if (mbmax < 1) return 0;
-    } else if (op == TC_OP_FWD || op == TC_OP_ADJ) {
+    } else if (op == TC_OP_FWD || op == TC_OP_ADJ || op == TC_OP_FWD_POL) {
         if (mbmax < 0 || mbmax > lmax) return 0;
     } else {
         return 0;
@@ -424,29 +525,19 @@ int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta, const d
                   double* C, void* workspace, size_t ws_bytes, void* stream)
 {
     g_error.clear();
-    int rc = check_sizes(lmax, mbmax);
-    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
-    if (!alm || !blm || !C) return fail(TC_EINVAL, "alm, blm or C is NULL");
-    if (!aligned16(alm) || !aligned16(blm) || !aligned16(C))
-        return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
-    const tc::Tile t = default_tile(TC_OP_FWD, lmax);
-    const Layout L = make_layout(TC_OP_FWD, lmax, mbmax, nring, cosbeta, t);
-    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    std::vector<char> img(L.tables_end, 0);
-    build_rings(nring, cosbeta, img, L);
-    build_slots(nring, cosbeta, img, L);
-    build_columns(lmax, mbmax, img, L);
-    if ((rc = upload(workspace, img, stream))) return rc;
-    tc::FwdArgs a{};
-    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
-    a.sky_lmax = lmax;
-    a.skip_exp = 100;
-    a.ring = ring_ptrs(workspace, L, nring);
-    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
-    a.col = col_ptrs(workspace, L);
-    a.alm = alm; a.blm = blm; a.C = C;
-    rc = timed_launch(TC_OP_FWD, stream, [&] { return tc::launch_fwd(a, t, stream); });
-    return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
+    return fwd_impl(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 1, &alm, &blm, 0, &C, workspace, ws_bytes, stream);
+}
+
+int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+                      const double* const* blm, int mode, double* const* C, void* workspace, size_t ws_bytes,
+                      void* stream)
+{
+    g_error.clear();
+    if (npair < 1 || npair > 3) return fail(TC_EINVAL, "npair = %d outside [1, 3]", npair);
+    if (mode != TC_POL_SEPARATE && mode != TC_POL_SUM) return fail(TC_EINVAL, "unknown mode %d", mode);
+    if (!alm || !blm || !C) return fail(TC_EINVAL, "alm, blm or C pointer array is NULL");
+    return fwd_impl(TC_OP_FWD_POL, lmax, mbmax, nring, cosbeta, npair, alm, blm, mode == TC_POL_SUM ? 1 : 0, C,
+                    workspace, ws_bytes, stream);
 }
 
 int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
@@ -454,38 +545,20 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const d
                   void* stream)
 {
     g_error.clear();
-    int rc = check_sizes(lmax, mbmax);
-    if (rc || (rc = check_rings(nring, cosbeta))) return rc;
-    if (!alm || !blm || !Cbar) return fail(TC_EINVAL, "alm, blm or Cbar is NULL");
-    if (!aligned16(alm) || !aligned16(blm) || !aligned16(Cbar) || (alm_bar && !aligned16(alm_bar)) ||
-        (blm_bar && !aligned16(blm_bar)))
-        return fail(TC_EINVAL, "complex arrays must be 16-byte aligned");
-    if (!alm_bar && !blm_bar) return TC_OK;   // nothing requested
-    const tc::Tile t = default_tile(TC_OP_ADJ, lmax);
-    const Layout L = make_layout(TC_OP_ADJ, lmax, mbmax, nring, cosbeta, t);
-    if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    std::vector<char> img(L.tables_end, 0);
-    build_rings(nring, cosbeta, img, L);
-    build_slots(nring, cosbeta, img, L);
-    build_columns(lmax, mbmax, img, L);
-    if ((rc = upload(workspace, img, stream))) return rc;
-    tc::AdjArgs a{};
-    a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
-    a.skip_exp = 100;
-    a.ring = ring_ptrs(workspace, L, nring);
-    a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
-    a.col = col_ptrs(workspace, L);
-    a.Cbar = Cbar;
-    a.U = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
-    a.V = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
-    a.P = L.P;
-    rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
-    if (rc) return hip_fail(rc, "totalconv_adj launch");
-    tc::EpiArgs e{};
-    e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax;
-    e.U = a.U; e.V = a.V; e.alm = alm; e.blm = blm; e.alm_bar = alm_bar; e.blm_bar = blm_bar;
-    rc = tc::launch_adj_epilogue(e, stream);
-    return rc ? hip_fail(rc, "totalconv_adj epilogue launch") : TC_OK;
+    return adj_impl(lmax, mbmax, nring, cosbeta, 1, &alm, &blm, 0, &Cbar, &alm_bar, &blm_bar, workspace, ws_bytes,
+                    stream);
+}
+
+int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+                      const double* const* blm, int mode, const double* const* Cbar, double* const* alm_bar,
+                      double* const* blm_bar, void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    if (npair < 1 || npair > 3) return fail(TC_EINVAL, "npair = %d outside [1, 3]", npair);
+    if (mode != TC_POL_SEPARATE && mode != TC_POL_SUM) return fail(TC_EINVAL, "unknown mode %d", mode);
+    if (!alm || !blm || !Cbar) return fail(TC_EINVAL, "alm, blm or Cbar pointer array is NULL");
+    return adj_impl(lmax, mbmax, nring, cosbeta, npair, alm, blm, mode == TC_POL_SUM ? 1 : 0, Cbar, alm_bar,
+                    blm_bar, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"
@@ -631,7 +704,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             a.ring = ring_ptrs(ws, L, d.nring);
             a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
             a.col = col_ptrs(ws, L);
-            a.alm = alm; a.blm = d.blm; a.C = d.C;
+            a.npair = 1; a.sum = 0; a.alm[0] = alm; a.blm[0] = d.blm; a.C[0] = d.C;
         } else {
             tc::AdjArgs& a = aa[i];
             a = tc::AdjArgs{};

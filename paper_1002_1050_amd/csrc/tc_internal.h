@@ -47,9 +47,11 @@ struct FwdArgs {
     RingTables ring;
     const int* slots;      // [nslot][2] (ring j, mirror ring or -1)
     ColumnTables col;
-    const double* alm;     // packed sky (complex)
-    const double* blm;     // [2M+1][L+1] complex
-    double* C;             // [2M+1][L+1][nring] complex
+    int npair;             // (sky, beam) pairs: 1 scalar, up to 3 polarised (temperature, gradient, curl)
+    int sum;               // polarised: 1 = one output, the sum over the pairs; 0 = one output per pair
+    const double* alm[3];  // packed sky of each pair (complex)
+    const double* blm[3];  // [2M+1][L+1] complex, per pair
+    double* C[3];          // [2M+1][L+1][nring] complex, per output
 };
 
 struct AdjArgs {

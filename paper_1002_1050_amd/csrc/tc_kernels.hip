@@ -41,6 +41,11 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 template <int R>
 constexpr int min_waves() { return R >= 8 ? 2 : (R >= 4 ? 3 : 4); }
 
+// Polarised forward: NC outputs carry 4 NC sums per chain and the staging lanes hold
+// NP pairs of raw weights, so the budget is one step lower than the scalar kernel's.
+template <int R, int NC, int NP>
+constexpr int fwd_min_waves() { return (NC == 1 && NP == 1) ? min_waves<R>() : (R >= 4 ? 2 : 3); }
+
 // The adjoint's LDS (about 53 KB per workgroup with TB = 32, 62 KB with TB = 64)
 // caps residency at 3 or 2 workgroups (waves per SIMD) per CU.
 template <int R, int TB>
@@ -290,18 +295,21 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
 }
 
 // ================================================================== forward
-// Weights of step l: w1 = conj(b_{l,mb}) s_{l,msky} for the direct ring and
-// w2 = (-1)^(l-msky) conj(b_{l,-mb}) s_{l,msky} for the mirror ring.
+// Weights of step l for the (sky, beam) pair p: w1 = conj(b^p_{l,mb}) s^p_{l,msky} for
+// the direct ring and w2 = (-1)^(l-msky) conj(b^p_{l,-mb}) s^p_{l,msky} for the mirror
+// ring.  Scalar convolution: one pair.  Polarised convolution (footnote of Sec. 4.1):
+// the temperature, gradient and curl pairs share the recursion, each with its own
+// weights (NC = NP outputs) or with their weights summed (one output, NC = 1).
 struct RawW {
     double br, bi, b2r, b2i, sr, si;
 };
 
-__device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int l, int mb, int ms)
+__device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int p, int l, int mb, int ms)
 {
     RawW w{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (l <= a.lmax) {
-        const double2* blm = reinterpret_cast<const double2*>(a.blm);
-        const double2* alm = reinterpret_cast<const double2*>(a.alm);
+        const double2* blm = reinterpret_cast<const double2*>(a.blm[p]);
+        const double2* alm = reinterpret_cast<const double2*>(a.alm[p]);
         const double2 b1 = blm[(size_t)(mb + a.mbmax) * (a.lmax + 1) + l];
         const double2 b2 = blm[(size_t)(-mb + a.mbmax) * (a.lmax + 1) + l];
         const double2 s = alm[packed_index(a.sky_lmax, l, ms)];
@@ -310,7 +318,7 @@ __device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int l, int mb
     return w;
 }
 
-__device__ __forceinline__ void finish_weights(const RawW& w, int l, int ms, double4& out)
+__device__ __forceinline__ double4 pair_weights(const RawW& w, int l, int ms)
 {
     // conj(b) * s
     const double w1r = w.br * w.sr + w.bi * w.si;
@@ -318,26 +326,58 @@ __device__ __forceinline__ void finish_weights(const RawW& w, int l, int ms, dou
     const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
     const double w2r = sg * (w.b2r * w.sr + w.b2i * w.si);
     const double w2i = sg * (w.b2r * w.si - w.b2i * w.sr);
-    out = make_double4(w1r, w1i, w2r, w2i);
+    return make_double4(w1r, w1i, w2r, w2i);
 }
 
-template <int R, bool ACC>
-__device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
+// Output c's weights from the raw loads of the NP pairs: pair c itself, or (NC = 1)
+// the sum over all pairs in pair order.
+template <int NC, int NP>
+__device__ __forceinline__ double4 output_weights(const RawW (&raw)[NP], int c, int l, int ms)
+{
+    if (NC == NP) return pair_weights(raw[c], l, ms);
+    double4 w = pair_weights(raw[0], l, ms);
+#pragma unroll
+    for (int p = 1; p < NP; ++p) {
+        const double4 v = pair_weights(raw[p], l, ms);
+        w.x += v.x; w.y += v.y; w.z += v.z; w.w += v.w;
+    }
+    return w;
+}
+
+template <int NC, int NP>
+__device__ __forceinline__ void stage_block(const FwdArgs& a, const RawW (&raw)[NP], int l, int mb, int ms,
+                                            double4 (&slot)[1 + NC])
+{
+    double A, nB, F2;
+    recursion_coefs(l, mb, ms, a.lmax, A, nB, F2);
+    slot[0] = make_double4(A, nB, F2, 0.0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) slot[1 + c] = output_weights<NC, NP>(raw, c, l, ms);
+}
+
+template <int R, int NC, bool ACC>
+__device__ __forceinline__ void fwd_steps(const double4 (*cf)[1 + NC], int s0,
                                           const double (&x)[R], double (&d)[R], double (&dp)[R],
-                                          double (&c1r)[R], double (&c1i)[R], double (&c2r)[R], double (&c2i)[R])
+                                          double (&c1r)[NC][R], double (&c1i)[NC][R],
+                                          double (&c2r)[NC][R], double (&c2i)[NC][R])
 {
 #pragma unroll
     for (int t = 0; t < TS; ++t) {
         const double4 k = cf[s0 + t][0];
-        double4 w;
-        if (ACC) w = cf[s0 + t][1];
+        double4 w[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (ACC) w[c] = cf[s0 + t][1 + c];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ACC) {
-                c1r[r] = fma(w.x, d[r], c1r[r]);
-                c1i[r] = fma(w.y, d[r], c1i[r]);
-                c2r[r] = fma(w.z, d[r], c2r[r]);
-                c2i[r] = fma(w.w, d[r], c2i[r]);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    c1r[c][r] = fma(w[c].x, d[r], c1r[c][r]);
+                    c1i[c][r] = fma(w[c].y, d[r], c1i[c][r]);
+                    c2r[c][r] = fma(w[c].z, d[r], c2r[c][r]);
+                    c2i[c][r] = fma(w[c].w, d[r], c2i[c][r]);
+                }
             }
             const double u = fma(x[r], k.x, k.y);
             const double dn = fma(-k.z, dp[r], u * d[r]);
@@ -347,11 +387,12 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[2], int s0,
     }
 }
 
-// One (column, ring tile) work item of the forward.  cf: {A, nB, F2, -}, {w1r, w1i, w2r, w2i}
-// per l of the current and the next block.
-template <int R, int NT, int TB>
-__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][2])
+// One (column, ring tile) work item of the forward.  cf per l of the current and the
+// next block: {A, nB, F2, -}, then {w1r, w1i, w2r, w2i} of each output.
+template <int R, int NT, int TB, int NC, int NP>
+__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][1 + NC])
 {
+    static_assert(NC == 1 || NC == NP, "one output per pair, or one summed output");
     const int tid = threadIdx.x;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
@@ -359,14 +400,17 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     const SeedShape sh = seed_shape(mb, ms);
     const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
 
-    double x[R], d[R], dp[R], c1r[R], c1i[R], c2r[R], c2i[R];
+    double x[R], d[R], dp[R], c1r[NC][R], c1i[NC][R], c2r[NC][R], c2i[NC][R];
     int E[R], jd[R], jm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int s = tile * (NT * R) + r * NT + tid;
         jd[r] = -1; jm[r] = -1;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
-        c1r[r] = 0.0; c1i[r] = 0.0; c2r[r] = 0.0; c2i[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            c1r[c][r] = 0.0; c1i[c][r] = 0.0; c2r[c][r] = 0.0; c2i[c][r] = 0.0;
+        }
         if (s < a.nslot) {
             jd[r] = a.slots[2 * s];
             jm[r] = a.slots[2 * s + 1];
@@ -382,21 +426,22 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     bool acc_on = (a.skip_exp <= 0);
 
     const int st = stage_slot<NT, TB>(tid);
+    RawW raw[NP];
     if (st >= 0) {
-        const int l = l0 + st;
-        double A, nB, F2;
-        recursion_coefs(l, mb, ms, L, A, nB, F2);
-        cf[0][st][0] = make_double4(A, nB, F2, 0.0);
-        finish_weights(load_weights_raw(a, l, mb, ms), l, ms, cf[0][st][1]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, l0 + st, mb, ms);
+        stage_block<NC, NP>(a, raw, l0 + st, mb, ms, cf[0][st]);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
     for (int kb = 0; kb < nblk; ++kb) {
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
-        RawW raw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const bool stage = (st >= 0) && (kb + 1 < nblk);
-        if (stage) raw = load_weights_raw(a, lb + TB + st, mb, ms);   // in flight during the block
+        if (stage) {   // in flight during the block
+#pragma unroll
+            for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, lb + TB + st, mb, ms);
+        }
         for (int s0 = 0; s0 < TB; s0 += TS) {
             if (scaled || !acc_on) {
                 bool any = false, hot = false;
@@ -405,8 +450,11 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
                     int k;
                     hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, scaled, k);
                     if (scaled && acc_on) {   // sums in the chain's scaled units follow it
-                        c1r[r] = ldexp(c1r[r], k); c1i[r] = ldexp(c1i[r], k);
-                        c2r[r] = ldexp(c2r[r], k); c2i[r] = ldexp(c2i[r], k);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            c1r[c][r] = ldexp(c1r[c][r], k); c1i[c][r] = ldexp(c1i[c][r], k);
+                            c2r[c][r] = ldexp(c2r[c][r], k); c2i[c][r] = ldexp(c2i[c][r], k);
+                        }
                     }
                     any |= (E[r] < 0);
                 }
@@ -414,39 +462,36 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
                 if (!acc_on) acc_on = wave_any(hot);
             }
             if (acc_on)
-                fwd_steps<R, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
             else
-                fwd_steps<R, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
         }
-        if (stage) {
-            const int l = lb + TB + st;
-            double A, nB, F2;
-            recursion_coefs(l, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][st][0] = make_double4(A, nB, F2, 0.0);
-            finish_weights(raw, l, ms, cf[buf ^ 1][st][1]);
-        }
+        if (stage) stage_block<NC, NP>(a, raw, lb + TB + st, mb, ms, cf[buf ^ 1][st]);
         __syncthreads();
     }
 
-    double2* C = reinterpret_cast<double2*>(a.C);
     const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (jd[r] >= 0) {
-            C[row_d + jd[r]] = make_double2(ldexp(c1r[r], E[r]), ldexp(c1i[r], E[r]));
-            if (jm[r] >= 0)
-                C[row_m + jm[r]] = make_double2(ldexp(c2r[r], E[r]), ldexp(c2i[r], E[r]));
+    for (int c = 0; c < NC; ++c) {
+        double2* C = reinterpret_cast<double2*>(a.C[c]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (jd[r] >= 0) {
+                C[row_d + jd[r]] = make_double2(ldexp(c1r[c][r], E[r]), ldexp(c1i[c][r], E[r]));
+                if (jm[r] >= 0)
+                    C[row_m + jm[r]] = make_double2(ldexp(c2r[c][r], E[r]), ldexp(c2i[c][r], E[r]));
+            }
         }
     }
 }
 
-template <int R, int NT, int TB>
-__global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd(const FwdArgs a)
+template <int R, int NT, int TB, int NC, int NP>
+__global__ void __launch_bounds__(NT, (fwd_min_waves<R, NC, NP>())) k_fwd(const FwdArgs a)
 {
-    __shared__ double4 cf[2][TB][2];
+    __shared__ double4 cf[2][TB][1 + NC];
     const int ci = blockIdx.x / a.ntile;
-    fwd_column<R, NT, TB>(a, ci, blockIdx.x - ci * a.ntile, cf);
+    fwd_column<R, NT, TB, NC, NP>(a, ci, blockIdx.x - ci * a.ntile, cf);
 }
 
 // Persistent form: each workgroup takes (detector, column, tile) items from a
@@ -464,7 +509,7 @@ __global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd_queue(const FwdArgs*
         __syncthreads();
         if (it >= nitems) break;
         const FwdArgs a = dets[items[3 * it]];
-        fwd_column<R, NT, TB>(a, items[3 * it + 1], items[3 * it + 2], cf);
+        fwd_column<R, NT, TB, 1, 1>(a, items[3 * it + 1], items[3 * it + 2], cf);
     }
 }
 
@@ -795,7 +840,8 @@ int launch_grid(void (*kern)(Args), const Args& a, int blocks, int nt, void* str
 }  // namespace
 
 // Built tile variants.  Forward and adjoint: R in {2, 4, 8}, TB in {32, 64};
-// adjoint reductions every TR = 4 steps.  Wigner: R in {1, 4}, TB = 32.
+// adjoint reductions every TR = 4 steps.  Polarised forward (op 3): R in {2, 4},
+// TB in {32, 64}.  Wigner: R in {1, 4}, TB = 32.
 bool tile_supported(int op, Tile t)
 {
     if (t.NT != 256) return false;
@@ -804,6 +850,7 @@ bool tile_supported(int op, Tile t)
     const bool tb_ok = t.TB == 32 || t.TB == 64;
     if (op == 1) return r_ok && tb_ok;
     if (op == 2) return r_ok && tb_ok && t.TR == 4;
+    if (op == 3) return (t.R == 2 || t.R == 4) && tb_ok;
     return false;
 }
 
@@ -819,13 +866,26 @@ int launch_wigner(const WignerArgs& a, Tile t, void* stream)
 
 // Maps a runtime (R, TB[, TR]) onto the template instantiation F<R, TB[, TR]>.
 #define TC_FWD_VARIANTS(X) X(2, 32) X(4, 32) X(8, 32) X(2, 64) X(4, 64) X(8, 64)
+#define TC_FWDPOL_VARIANTS(X)                                                                   \
+    X(2, 32, 1, 2) X(4, 32, 1, 2) X(2, 64, 1, 2) X(4, 64, 1, 2) X(2, 32, 1, 3) X(4, 32, 1, 3)  \
+    X(2, 64, 1, 3) X(4, 64, 1, 3) X(2, 32, 2, 2) X(4, 32, 2, 2) X(2, 64, 2, 2) X(4, 64, 2, 2)  \
+    X(2, 32, 3, 3) X(4, 32, 3, 3) X(2, 64, 3, 3) X(4, 64, 3, 3)
 #define TC_ADJ_VARIANTS(X) X(2, 32, 4) X(4, 32, 4) X(8, 32, 4) X(2, 64, 4) X(4, 64, 4) X(8, 64, 4)
 
 int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 {
     const int blocks = a.ncol * a.ntile;
-#define X(r, tb) if (t.R == r && t.TB == tb) return launch_grid(k_fwd<r, 256, tb>, a, blocks, 256, stream);
-    TC_FWD_VARIANTS(X)
+    if (a.npair == 1) {
+#define X(r, tb) if (t.R == r && t.TB == tb) return launch_grid(k_fwd<r, 256, tb, 1, 1>, a, blocks, 256, stream);
+        TC_FWD_VARIANTS(X)
+#undef X
+        return (int)hipErrorInvalidValue;
+    }
+    const int nc = a.sum ? 1 : a.npair;
+#define X(r, tb, c, p)                                                        \
+    if (t.R == r && t.TB == tb && nc == c && a.npair == p)                    \
+        return launch_grid(k_fwd<r, 256, tb, c, p>, a, blocks, 256, stream);
+    TC_FWDPOL_VARIANTS(X)
 #undef X
     return (int)hipErrorInvalidValue;
 }

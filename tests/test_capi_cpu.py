@@ -112,7 +112,29 @@ def test_timing_arguments_checked_on_host(L):
     buf = (ctypes.c_float * 4)()
     assert L.tc_timing_enable(-1) == -1
     assert L.tc_timing_enable(65537) == -1
-    assert L.tc_timing_read(3, buf, 4) == -1
+    assert L.tc_timing_read(4, buf, 4) == -1
     assert L.tc_timing_read(1, None, 4) == -1
     assert L.tc_timing_read(1, buf, 4) == 0          # timing off: nothing recorded
     assert L.tc_timing_enable(0) == 0
+
+
+def test_polarised_arguments_checked_on_host(L):
+    from paper_1002_1050_amd import _binding as B
+    x = np.linspace(-1, 1, 11)
+    xp = x.ctypes.data_as(ctypes.c_void_p)
+    fake = [0x200000, 0x300000, 0x400000]
+    arr = (ctypes.c_void_p * 3)(*fake)
+    ws = ctypes.c_void_p(0x100000)
+    for npair, mode in ((0, 0), (4, 0), (2, 2), (2, -1)):
+        assert L.totalconv_fwd_pol(10, 2, x.size, xp, npair, arr, arr, mode, arr, ws, 1 << 30, None) == -1
+        assert L.totalconv_adj_pol(10, 2, x.size, xp, npair, arr, arr, mode, arr, arr, arr, ws, 1 << 30,
+                                   None) == -1
+    holed = (ctypes.c_void_p * 3)(fake[0], None, fake[2])
+    assert L.totalconv_fwd_pol(10, 2, x.size, xp, 3, arr, holed, 0, arr, ws, 1 << 30, None) == -1
+    assert "pair 1" in B.last_error()
+    assert L.totalconv_fwd_pol(10, 2, x.size, xp, 3, arr, arr, 0, holed, ws, 1 << 30, None) == -1
+    assert "output 1" in B.last_error()
+    assert L.totalconv_fwd_pol(10, 2, x.size, xp, 2, None, arr, 0, arr, ws, 1 << 30, None) == -1
+    # summed mode needs one cotangent only; nothing requested is a no-op
+    one = (ctypes.c_void_p * 1)(fake[0])
+    assert L.totalconv_adj_pol(10, 2, x.size, xp, 3, arr, arr, 1, one, None, None, ws, 1 << 30, None) == 0

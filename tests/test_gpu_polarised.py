@@ -1,0 +1,134 @@
+"""Polarised total convolution (temperature, gradient and curl pairs sharing one
+recursion) against the oracle, which evaluates eq. convdef for each pair (footnote of
+Sec. 4.1), through the C ABI.  Gates as in test_gpu_parity: per column for C, normwise
+(sky) and per mb row (beam) for the gradients, 1e-11."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1002_1050_amd import synthetic as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-11
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1002_1050_amd import _binding
+    _binding.lib()
+    yield _binding
+    _binding.set_tile_ex(_binding.TC_OP_FWD_POL, 0, 0, 0)
+    _binding.set_tile_ex(_binding.TC_OP_FWD, 0, 0, 0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def column_gate(got, ref):
+    got = got.reshape(-1, got.shape[-1])
+    ref = ref.reshape(-1, ref.shape[-1])
+    num = np.abs(got - ref).max(axis=1)
+    den = np.abs(ref).max(axis=1)
+    assert np.all(num[den == 0] == 0), "non-zero result in an all-zero column"
+    return float((num[den > 0] / den[den > 0]).max())
+
+
+def pairs(L, M, n, seed):
+    alms = [S.sky_alm(L, seed + p) for p in range(n)]
+    blms = [S.random_beam(L, M, seed + 10 + p) for p in range(n)]
+    return alms, blms
+
+
+# 2600 rings: 1300 mirror slots, so two ring tiles at R = 4 and three at R = 2
+CASES = [(120, 4, 2600), (70, 9, 301)]
+
+
+@pytest.mark.parametrize("R,TB", [(2, 32), (4, 64)])
+@pytest.mark.parametrize("npair", [2, 3])
+def test_polarised_forward_separate_and_summed(B, orc, R, TB, npair):
+    for L, M, n in CASES:
+        x = S.ring_cosines(n)
+        alms, blms = pairs(L, M, npair, 100 + L)
+        da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+        B.set_tile_ex(B.TC_OP_FWD_POL, R, TB, 0)
+        say(f"fwd_pol L={L} M={M} nring={n} npair={npair} R={R} TB={TB}")
+        sep = [c.cpu().numpy() for c in B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SEPARATE)]
+        tot = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
+        ref = orc.totalconv_fwd_pol(L, M, x, alms, blms)
+        gs = max(column_gate(sep[p], ref[p]) for p in range(npair))
+        gt = column_gate(tot, sum(ref))
+        say(f"  separate {gs:.2e}, summed {gt:.2e}")
+        assert gs <= GATE and gt <= GATE
+        # each separate output is the scalar forward of its pair, same tile: same arithmetic
+        B.set_tile_ex(B.TC_OP_FWD, R, TB, 0)
+        for p in range(npair):
+            plain = B.totalconv_fwd(L, M, x, da[p], db[p]).cpu().numpy()
+            assert np.array_equal(plain, sep[p]), f"pair {p}: polarised output != scalar forward"
+
+
+def test_polarised_single_pair_is_scalar(B, orc):
+    L, M, n = 90, 5, 400
+    x = S.ring_cosines(n)
+    alms, blms = pairs(L, M, 1, 7)
+    da, db = [dev(alms[0])], [dev(blms[0])]
+    say("fwd_pol npair=1")
+    got = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
+    ref = orc.totalconv_fwd(L, M, x, alms[0], blms[0])
+    assert column_gate(got, ref) <= GATE
+
+
+@pytest.mark.parametrize("summed", [True, False])
+def test_polarised_adjoint(B, orc, summed):
+    L, M, n = 150, 6, 1200
+    x = S.ring_cosines(n)
+    alms, blms = pairs(L, M, 3, 300)
+    da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+    nG = 1 if summed else 3
+    Gs = [S.random_cbar(L, M, n, 500 + k) for k in range(nG)]
+    mode = B.TC_POL_SUM if summed else B.TC_POL_SEPARATE
+    say(f"adj_pol L={L} M={M} nring={n} summed={summed}")
+    ga, gb = B.totalconv_adj_pol(L, M, x, da, db, [dev(g) for g in Gs], mode)
+    ra, rb = orc.totalconv_adj_pol(L, M, x, alms, blms, Gs, summed=summed)
+    for p in range(3):
+        a = ga[p].cpu().numpy()
+        b = gb[p].cpu().numpy()
+        ea = np.linalg.norm(a - ra[p]) / np.linalg.norm(ra[p])
+        eb = max(np.linalg.norm(b[r] - rb[p][r]) / np.linalg.norm(rb[p][r])
+                 for r in range(2 * M + 1) if np.any(rb[p][r] != 0))
+        say(f"  pair {p}: sky {ea:.2e}, beam {eb:.2e}")
+        assert ea <= GATE and eb <= GATE
+    # only the beam gradients requested: the sky arrays stay untouched (None)
+    ga2, gb2 = B.totalconv_adj_pol(L, M, x, da, db, [dev(g) for g in Gs], mode, want_alm=False)
+    assert all(g is None for g in ga2)
+    for p in range(3):
+        assert torch.equal(gb2[p], gb[p])
+
+
+def test_polarised_rejects_bad_arguments(B):
+    L, M = 20, 2
+    x = S.ring_cosines(41)
+    alms, blms = pairs(L, M, 3, 1)
+    da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+    lib = B.lib()
+    arr = B._ptr_array
+    out = [torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda") for _ in range(4)]
+    ws = torch.empty(B.workspace_bytes(B.TC_OP_FWD_POL, L, M, x), dtype=torch.uint8, device="cuda")
+    xp = x.ctypes.data_as(B.ctypes.c_void_p)
+    for npair, mode in ((4, 0), (0, 0), (2, 2)):
+        rc = lib.totalconv_fwd_pol(L, M, x.size, xp, npair, arr(da + da), arr(db + db), mode, arr(out),
+                                   B._dptr(ws), ws.numel(), None)
+        assert rc == -1, (npair, mode)
+    rc = lib.totalconv_fwd_pol(L, M, x.size, xp, 3, arr(da[:2] + [None]), arr(db), 0, arr(out),
+                               B._dptr(ws), ws.numel(), None)
+    assert rc == -1 and "pair 2" in B.last_error()

@@ -263,3 +263,40 @@ def test_invalid_conv_arguments(orc):
     with pytest.raises(ValueError):
         orc.totalconv_fwd(4, 1, xr, S.sky_alm(4, 1), np.zeros((3, 5), complex),
                           cols=(np.array([2], np.int32), np.array([0], np.int32)))
+
+
+def test_polarised_pairs_against_brute_force(orc):
+    """Footnote of Sec. 4.1: the polarised convolution is eq. convdef for each of the
+    temperature, gradient and curl pairs.  Separate outputs and their sum against mpmath
+    sums of explicit-sum d; the adjoint pairs against the dot-product identity."""
+    mp.mp.dps = 40
+    from oracle import mpref
+    L, M, n = 7, 2, 5
+    xr = rings(n)
+    alms = [random_sky(L, 30 + p) for p in range(3)]
+    blms = [S.random_beam(L, M, 40 + p) for p in range(3)]
+    sep = orc.totalconv_fwd_pol(L, M, xr, alms, blms)
+    tot = orc.totalconv_fwd_pol(L, M, xr, alms, blms, summed=True)
+    assert len(sep) == 3 and len(tot) == 1
+    worst = 0.0
+    for mb in range(-M, M + 1):
+        for ms in range(0, L + 1):
+            for j in range(n):
+                refs = [mpref.conv_brute(L, mb, ms, xr[j], sky_get(alms[p], L), beam_get(blms[p], M))
+                        for p in range(3)]
+                for p in range(3):
+                    worst = max(worst, abs(sep[p][mb + M, ms, j] - refs[p]))
+                worst = max(worst, abs(tot[0][mb + M, ms, j] - sum(refs)))
+    assert worst <= 1e-14, worst
+    # adjoint: <C(a, b), G> = <a, sky_bar> + (b-part) per pair, with the summed output's cotangent
+    G = S.random_cbar(L, M, n, 50)
+    sky_bar, beam_bar = orc.totalconv_adj_pol(L, M, xr, alms, blms, [G], summed=True)
+    lhs = np.vdot(G, tot[0])                            # <G, C> = sum conj(G) C
+    rhs = 0j
+    for p in range(3):
+        # C is complex-linear in s: <G, C(s)> = <sky_bar, s> restricted to the stored half-set
+        rhs += np.vdot(sky_bar[p], alms[p])
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # conj-linear in b: <G, C> = sum conj(b) (s d conj(G)) = <b, beam_bar>
+    rhs_b = sum(np.vdot(blms[p], beam_bar[p]) for p in range(3))
+    assert abs(lhs - rhs_b) <= 1e-12 * abs(lhs)
