@@ -68,6 +68,8 @@ def parse():
                    help="interleaved repetitions of the sixteen-detector batched-vs-plain comparison (0 skips)")
     p.add_argument("--pol-reps", type=int, default=2,
                    help="timed repetitions of the polarised forward (three pairs, separate and summed; 0 skips)")
+    p.add_argument("--cube-reps", type=int, default=2,
+                   help="timed repetitions of the data-cube stage on the forward's output (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
     p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB' (skips its autotuning)")
@@ -197,6 +199,33 @@ def batched_compare(reps, tune):
     }
     plan.close()
     return res
+
+
+def datacube_timing(w, C, reps):
+    """Data cube of eq. conviqt from the forward's C: nalpha = 2 mbmax + 1, ngamma = 2 lmax.
+    Algorithmic bytes: C read once, the cube written once."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    na, ng = 2 * w.mbmax + 1, 2 * w.lmax
+    cube = torch.empty((w.nring, na, ng), dtype=torch.float64, device=C.device)
+    B.totalconv_datacube(w.lmax, w.mbmax, C, na, ng, out=cube)   # warm-up
+    torch.cuda.synchronize()
+    B.timing_enable(64)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.totalconv_datacube(w.lmax, w.mbmax, C, na, ng, out=cube)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    chunks = B.timing_read(B.TC_OP_CUBE, 64)
+    B.timing_enable(0)
+    kms = float(np.sum(chunks)) / reps
+    nbytes = C.numel() * 16 + cube.numel() * 8
+    del cube
+    torch.cuda.empty_cache()
+    log(f"  data cube: kernels {kms:.2f} ms ({len(chunks) // reps} ring chunks), {nbytes / (kms * 1e-3) / 1e9:.0f} GB/s")
+    return {"workload": f"data cube, nalpha={na}, ngamma={ng}, {w.nring} rings, lmax={w.lmax}, mbmax={w.mbmax}",
+            "kernel_ms": round(kms, 3), "call_ms": round(wall * 1e3, 3), "algorithmic_bytes": nbytes,
+            "hbm_gb_per_s": nbytes / (kms * 1e-3) / 1e9, "ring_chunks": len(chunks) // reps}
 
 
 def polarised_compare(w, x, alm, blm, reps, tune):
@@ -385,6 +414,9 @@ def main():
         "roofline": roofline,
         "tiles_R_TB_TR": tiles,
     }
+    if args.cube_reps > 0 and not args.fwd_only:
+        log("data cube")
+        result["datacube"] = datacube_timing(w, C, args.cube_reps)
     if args.cpu_seconds > 0:
         nring = w.nring
         Gc = G.reshape(-1, nring)

@@ -57,6 +57,7 @@ extern "C" {
 #define TC_OP_FWD 1
 #define TC_OP_ADJ 2
 #define TC_OP_FWD_POL 3       /* tiles / workspace of totalconv_fwd_pol */
+#define TC_OP_CUBE 4          /* timing of totalconv_datacube */
 
 #define TC_POL_SEPARATE 0     /* polarised: one output per (sky, beam) pair */
 #define TC_POL_SUM 1          /* polarised: one output, the sum over the pairs */
@@ -171,6 +172,33 @@ int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int
                       void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Data cube (Sec. 4.1, eq. conviqt): from the coefficients C of totalconv_fwd,
+ *   cube[j][a][g] = c(alpha_a, beta_j, gamma_g)
+ *                 = sum_{mb=-mbmax}^{mbmax} sum_{msky=-lmax}^{lmax}
+ *                   e^{-i mb alpha_a} e^{-i msky gamma_g} C_{mb,msky}(beta_j),
+ *   alpha_a = 2 pi a / nalpha (a < nalpha), gamma_g = 2 pi g / ngamma (g < ngamma),
+ * with the msky < 0 columns taken from C_{-mb,-msky} = conj(C_{mb,msky}) (real
+ * sky and beam, Sec. 4.2.3).  c is then real; the imaginary part that rounding
+ * (or a beam that is not real) leaves in the msky = 0 term is dropped.  The sum
+ * over mb is done directly, the one over msky by an FFT of length ngamma.
+ *   lmax, mbmax  0 <= mbmax <= lmax <= 8192
+ *   nring        >= 1; C as written by totalconv_fwd (device)
+ *   nalpha       >= 1, nalpha * (2*mbmax+1) <= 4096
+ *   ngamma       a power of two in [max(2, 2*lmax), 16384] (at 2*lmax the two
+ *                terms msky = +-lmax meet in one frequency, as the definition
+ *                evaluated on that grid requires)
+ *   cube         out: [nring][nalpha][ngamma] doubles, 16-byte aligned
+ *   workspace    at least totalconv_datacube_workspace_bytes(...) bytes: the
+ *                phase and twiddle tables and the alpha sums of one ring chunk
+ *                (at most 2 GiB; rings are processed in chunks)
+ * TC_EUNSUPPORTED if the device allows less LDS per workgroup than the FFT of
+ * length ngamma needs (8 * ngamma + 16 bytes).
+ */
+size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int nalpha, int ngamma);
+int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma,
+                       double* cube, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Tile selection for later calls in this process (not in the paper; a tuning
  * knob of this implementation).  Each lane walks R chains; a workgroup covers
  * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8}),
@@ -240,7 +268,8 @@ int tc_plan_destroy(void* plan);
  * from then on every wigner_d_rings / totalconv_fwd / totalconv_adj /
  * totalconv_fwd_pol call records one pair (under op TC_OP_WIGNER, TC_OP_FWD,
  * TC_OP_ADJ, TC_OP_FWD_POL) on its own stream, directly before and after its
- * recursion kernel (for the adjoint: without the two short epilogue kernels
+ * recursion kernel; totalconv_datacube records one TC_OP_CUBE pair around the
+ * two kernels of each ring chunk (for the adjoint: without the two short epilogue kernels
  * that finish the gradients; totalconv_adj_pol records one TC_OP_ADJ pair per
  * cotangent), reusing the pairs cyclically.  n = 0 releases the events and
  * stops the recording.  Calls must then run on streams of that device.

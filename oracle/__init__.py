@@ -56,6 +56,8 @@ def _load():
             lib.oracle_totalconv_fwd.argtypes = [I, I, I, P, P, P, I, P, P, I, P, ctypes.c_double, P, I]
             lib.oracle_totalconv_u.argtypes = [I, I, I, P, P, I, P, P, P, I]
             lib.oracle_ring_x.argtypes = [I, P, P]
+            lib.oracle_datacube.argtypes = [I, I, I, P, I, I, I, P, P, P, P, I]
+            lib.oracle_datacube.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             for f in (lib.oracle_wigner_d, lib.oracle_totalconv_fwd, lib.oracle_totalconv_u,
                       lib.oracle_ring_x, lib.oracle_max_threads):
@@ -232,3 +234,26 @@ def totalconv_adj_pol(lmax: int, mbmax: int, xring, alms, blms, Gbars, summed: b
         sky.append(sb)
         beam.append(bb)
     return sky, beam
+
+
+def datacube(lmax: int, mbmax: int, C, nalpha: int, ngamma: int, points=None, nthreads: int = 0):
+    """Data cube of eq. conviqt (Sec. 4.1) by its definition, the double sum over mb and
+    msky in [-lmax, lmax] with C_{mb,msky<0} = conj(C_{-mb,-msky}); real part.
+
+    C: complex (2*mbmax+1, lmax+1, nring).  points: (ring, a, g) index arrays, or None
+    for the whole cube, shape (nring, nalpha, ngamma)."""
+    C = _c(C, np.complex128)
+    nring = C.shape[-1]
+    if C.shape != (2 * mbmax + 1, lmax + 1, nring):
+        raise ValueError("C must have shape (2*mbmax+1, lmax+1, nring)")
+    if points is None:
+        j, a, g = np.meshgrid(np.arange(nring), np.arange(nalpha), np.arange(ngamma), indexing="ij")
+        pts = [_c(v.ravel(), np.int32) for v in (j, a, g)]
+    else:
+        pts = [_c(v, np.int32) for v in points]
+    out = np.empty(pts[0].size, np.float64)
+    rc = _load().oracle_datacube(lmax, mbmax, nring, _ptr(C), nalpha, ngamma, pts[0].size,
+                                 _ptr(pts[0]), _ptr(pts[1]), _ptr(pts[2]), _ptr(out), nthreads)
+    if rc:
+        raise ValueError("oracle_datacube: invalid arguments (%d)" % rc)
+    return out.reshape(nring, nalpha, ngamma) if points is None else out

@@ -19,6 +19,8 @@
  *                      long double range stay exact.
  *   convolution        Sec. 4.1 eq. convdef:
  *                      C_{mb,msky}(beta) = sum_l conj(b_{l,mb}) d^l_{mb,msky}(beta) s_{l,msky}.
+ *   data cube          Sec. 4.1 eq. conviqt: the double sum over mb and msky of
+ *                      e^{-i mb alpha} e^{-i msky gamma} C_{mb,msky}(beta), term by term.
  *
  * Readings of the paper taken here (the paper is silent or garbled there):
  *   - Seed rows (printed rows 2-4 all read d^l_{-l,m}):
@@ -423,4 +425,47 @@ int oracle_ring_x(int nring, const double* beta, double* x)
 int oracle_max_threads(void)
 {
     return omp_get_max_threads();
+}
+
+/* ------------------------------------------------------------------ data cube
+ * Sec. 4.1 eq. conviqt at sampled points, by the definition:
+ *   c(alpha_a, beta_j, gamma_g) = sum_{mb=-M}^{M} sum_{msky=-L}^{L}
+ *                                 e^{-i mb alpha_a} e^{-i msky gamma_g} C_{mb,msky}(beta_j),
+ *   alpha_a = 2 pi a / nalpha, gamma_g = 2 pi g / ngamma,
+ * where the columns with msky < 0 are C_{mb,msky} = conj(C_{-mb,-msky}) (real sky
+ * and beam, Sec. 4.2.3).  C: [2M+1][L+1][nring] complex (msky >= 0, as the forward
+ * writes it).  out[p] = Re c at point (ring[p], ia[p], ig[p]).
+ */
+static const ld PI_L = 3.14159265358979323846264338327950288L;
+
+int oracle_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma,
+                    int npts, const int* ring, const int* ia, const int* ig, double* out, int nthreads)
+{
+    if (lmax < 0 || mbmax < 0 || mbmax > lmax || nring < 1 || nalpha < 1 || ngamma < 1 || npts < 0)
+        return 1;
+    for (int p = 0; p < npts; ++p)
+        if (ring[p] < 0 || ring[p] >= nring || ia[p] < 0 || ia[p] >= nalpha || ig[p] < 0 || ig[p] >= ngamma)
+            return 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < npts; ++p) {
+        const int j = ring[p], a = ia[p], g = ig[p];
+        ld re = 0.0L;
+        for (int mb = -mbmax; mb <= mbmax; ++mb) {
+            for (int ms = -lmax; ms <= lmax; ++ms) {
+                /* C_{mb,ms}: stored for ms >= 0, else the conjugate of C_{-mb,-ms} */
+                const int smb = ms >= 0 ? mb : -mb, sms = ms >= 0 ? ms : -ms;
+                const double* z = C + 2 * (((size_t)(smb + mbmax) * (lmax + 1) + sms) * nring + j);
+                const ld cr = z[0], ci = ms >= 0 ? z[1] : -z[1];
+                /* phase e^{-i theta}, theta = 2 pi (mb a / nalpha + ms g / ngamma), reduced exactly */
+                const long long na = (((long long)mb * a) % nalpha + nalpha) % nalpha;
+                const long long ng = (((long long)ms * g) % ngamma + ngamma) % ngamma;
+                const ld th = 2.0L * PI_L * ((ld)na / (ld)nalpha + (ld)ng / (ld)ngamma);
+                /* Re(e^{-i th} (cr + i ci)) = cos(th) cr + sin(th) ci */
+                re += cosl(th) * cr + sinl(th) * ci;
+            }
+        }
+        out[p] = (double)re;
+    }
+    return 0;
 }

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtotalconv.so")
 
-TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL = 0, 1, 2, 3
+TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE = 0, 1, 2, 3, 4
 TC_POL_SEPARATE, TC_POL_SUM = 0, 1
 TC_LMAX_LIMIT = 16384
 
@@ -86,6 +86,10 @@ def lib():
             L.totalconv_fwd_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, P, S, P]
             L.totalconv_adj_pol.restype = I
             L.totalconv_adj_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, PP, PP, P, S, P]
+            L.totalconv_datacube_workspace_bytes.restype = S
+            L.totalconv_datacube_workspace_bytes.argtypes = [I, I, I, I, I]
+            L.totalconv_datacube.restype = I
+            L.totalconv_datacube.argtypes = [I, I, I, P, I, I, P, P, S, P]
             L.tc_timing_enable.restype = I
             L.tc_timing_enable.argtypes = [I]
             L.tc_timing_read.restype = I
@@ -282,6 +286,30 @@ def totalconv_adj_pol(lmax: int, mbmax: int, cosbeta, alms, blms, Cbars, mode=TC
                                  _ptr_array(bbar) if want_blm else None, _dptr(ws), ws.numel(), stream)
     _check("totalconv_adj_pol", rc)
     return abar, bbar
+
+
+def totalconv_datacube(lmax: int, mbmax: int, C, nalpha: int, ngamma: int, out=None):
+    """Data cube c(alpha_a, beta_j, gamma_g) of eq. conviqt from the coefficients C
+    (complex128 (2*mbmax+1, lmax+1, nring) on the GPU); float64 (nring, nalpha, ngamma)."""
+    import torch
+    _require_device(C, "C", torch.complex128)
+    if C.dim() != 3 or tuple(C.shape[:2]) != (2 * mbmax + 1, lmax + 1):
+        raise ValueError("C must have shape (2*mbmax+1, lmax+1, nring)")
+    nring = C.shape[2]
+    shape = (nring, nalpha, ngamma)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=C.device)
+    else:
+        _require_device(out, "out", torch.float64)
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {shape}")
+    stream = _stream_handle(torch, C.device)
+    nbytes = int(lib().totalconv_datacube_workspace_bytes(lmax, mbmax, nring, nalpha, ngamma))
+    ws = workspace_cache.get(torch, C.device, stream, nbytes)
+    rc = lib().totalconv_datacube(lmax, mbmax, nring, _dptr(C), nalpha, ngamma, _dptr(out), _dptr(ws),
+                                  ws.numel(), stream)
+    _check("totalconv_datacube", rc)
+    return out
 
 
 def set_tile(op: int, R: int):

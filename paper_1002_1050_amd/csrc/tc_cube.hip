@@ -1,0 +1,253 @@
+// gfx950 kernels of the data-cube stage (Sec. 4.1, eq. conviqt):
+//
+//   c(alpha_a, beta_j, gamma_g) = sum_{mb=-M}^{M} sum_{msky=-L}^{L}
+//                                 e^{-i mb alpha_a} e^{-i msky gamma_g} C_{mb,msky}(beta_j)
+//
+// on alpha_a = 2 pi a / nalpha, gamma_g = 2 pi g / ngamma, with the columns msky < 0
+// taken from C_{-mb,-msky} = conj(C_{mb,msky}) (real sky and beam, Sec. 4.2.3), so
+// that c is real.
+//
+// Two passes, both bound by HBM bandwidth:
+//  1. k_cube_alpha: P[j][a][k] = sum_mb E[a][mb] C[mb][k][j] for k = msky >= 0 -- the
+//     short sum over mb, done directly with the host's phase table E, and the
+//     transpose from ring-fastest C to rows (ring, alpha) with msky fastest.
+//  2. k_cube_gamma: one workgroup per row turns P_0..P_L into the real row
+//     c[g] = Re P_0 + 2 Re sum_{k>=1} P_k e^{-2 pi i k g / N}: the Hermitian
+//     spectrum is folded into its half X_0..X_{N/2}, packed into one complex
+//     sequence of length H = N/2 (even outputs in the real part, odd outputs in the
+//     imaginary part) and transformed by a Stockham FFT in LDS (radix-16 passes and
+//     one smaller one), twiddles from the host's table W^m = e^{-2 pi i m / N}.
+
+#include <hip/hip_runtime.h>
+
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// ------------------------------------------------------------ alpha sums
+constexpr int CA_T = 16;    // rings and msky values per workgroup tile (16 x 16 = 256 lanes)
+constexpr int CA_Q = 8;     // alpha values per transposed store
+
+template <int QA>
+__global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c)
+{
+    extern __shared__ double2 sh[];
+    const int nb = 2 * c.mbmax + 1;
+    double2* E = sh;                                 // [nalpha][nb]
+    double2* tile = sh + c.nalpha * nb;              // [CA_Q][CA_T][CA_T + 1]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < c.nalpha * nb; i += 256) E[i] = reinterpret_cast<const double2*>(c.phase)[i];
+    const int jj = tid & (CA_T - 1), kk = tid / CA_T;
+    const int j0 = blockIdx.x * CA_T, k0 = blockIdx.y * CA_T;
+    const int j = j0 + jj, k = k0 + kk;
+    const int L1 = c.lmax + 1;
+    const bool in = (j < c.nring_chunk) && (k <= c.lmax);
+    const double2* C = reinterpret_cast<const double2*>(c.C);
+    double2* P = reinterpret_cast<double2*>(c.P);
+    __syncthreads();
+    for (int a0 = 0; a0 < c.nalpha; a0 += QA) {
+        double ar[QA], ai[QA];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
+        if (in) {
+            const double2* src = C + (size_t)k * c.nring + (c.ring0 + j);
+            for (int mb = 0; mb < nb; ++mb) {
+                const double2 v = src[(size_t)mb * L1 * c.nring];
+#pragma unroll
+                for (int q = 0; q < QA; ++q) {
+                    if (a0 + q < c.nalpha) {
+                        const double2 e = E[(a0 + q) * nb + mb];
+                        ar[q] = fma(e.x, v.x, fma(-e.y, v.y, ar[q]));
+                        ai[q] = fma(e.x, v.y, fma(e.y, v.x, ai[q]));
+                    }
+                }
+            }
+        }
+        // transposed stores, CA_Q values of alpha at a time: lanes with consecutive msky
+#pragma unroll
+        for (int q0 = 0; q0 < QA; q0 += CA_Q) {
+            if (a0 + q0 >= c.nalpha) break;
+#pragma unroll
+            for (int q = 0; q < CA_Q; ++q)
+                tile[(q * CA_T + kk) * (CA_T + 1) + jj] = make_double2(ar[q0 + q], ai[q0 + q]);
+            __syncthreads();
+            const int jw = tid / CA_T, kw = tid & (CA_T - 1);
+            if (j0 + jw < c.nring_chunk && k0 + kw <= c.lmax) {
+                for (int q = 0; q < CA_Q && a0 + q0 + q < c.nalpha; ++q)
+                    P[((size_t)(j0 + jw) * c.nalpha + (a0 + q0 + q)) * L1 + (k0 + kw)] =
+                        tile[(q * CA_T + kw) * (CA_T + 1) + jw];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------ gamma FFT
+// Forward DFT of size R (sign -) in registers: bit-reversed reorder, then radix-2
+// stages with the 16th roots of unity as constants.
+__device__ __forceinline__ double2 root16(int m, double2 z)
+{
+    // z * e^{-2 pi i m / 16}, m in [0, 8)
+    constexpr double C1 = 0.9238795325112867;   // cos(pi/8)
+    constexpr double S1 = 0.3826834323650898;   // sin(pi/8)
+    constexpr double H2 = 0.7071067811865476;   // cos(pi/4)
+    switch (m) {
+    case 0: return z;
+    case 4: return make_double2(z.y, -z.x);
+    case 1: return cmul(z, make_double2(C1, -S1));
+    case 2: return cmul(z, make_double2(H2, -H2));
+    case 3: return cmul(z, make_double2(S1, -C1));
+    case 5: return cmul(z, make_double2(-S1, -C1));
+    case 6: return cmul(z, make_double2(-H2, -H2));
+    default: return cmul(z, make_double2(-C1, -S1));
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void dft_regs(double2 (&v)[R])
+{
+    constexpr int LOG = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < LOG; ++b) r |= ((i >> b) & 1) << (LOG - 1 - b);
+        if (i < r) {
+            const double2 t = v[i];
+            v[i] = v[r];
+            v[r] = t;
+        }
+    }
+#pragma unroll
+    for (int half = 1; half < R; half <<= 1) {
+#pragma unroll
+        for (int b = 0; b < R; b += 2 * half) {
+#pragma unroll
+            for (int q = 0; q < half; ++q) {
+                const double2 t = root16(q * (8 / half), v[b + q + half]);
+                v[b + q + half] = csub(v[b + q], t);
+                v[b + q] = cadd(v[b + q], t);
+            }
+        }
+    }
+}
+
+constexpr int CG_HMAX = 8192;   // largest half length (ngamma <= 16384)
+
+// One Stockham pass of radix R over X[0..H) in place (all reads, barrier, all writes).
+template <int R>
+__device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, const double2* __restrict__ tw)
+{
+    constexpr int GM = CG_HMAX / (R * 256);
+    const int tid = threadIdx.x;
+    const int ng = H / R;
+    double2 v[GM][R];
+#pragma unroll
+    for (int i = 0; i < GM; ++i) {
+        const int g = tid + 256 * i;
+        if (g < ng) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = X[g + r * ng];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < GM; ++i) {
+        const int g = tid + 256 * i;
+        if (g < ng) {
+            const int k = g & (Ns - 1);
+            const int step = N / (Ns * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[k * r * step]);
+            dft_regs<R>(v[i]);
+            const int base = (g - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) X[base + r * Ns] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
+{
+    extern __shared__ double2 X[];   // H + 1 entries
+    const int row = blockIdx.x;      // (ring within the chunk) * nalpha + alpha
+    const int N = c.ngamma, H = N / 2, L = c.lmax;
+    const int tid = threadIdx.x;
+    const double2* P = reinterpret_cast<const double2*>(c.P) + (size_t)row * (L + 1);
+    const double2* tw = reinterpret_cast<const double2*>(c.tw);
+    // half spectrum X_b = Z_b + Z_{b-N}, Z_0 = Re P_0, Z_k = P_k, Z_{-k} = conj(P_k)
+    for (int b = tid; b <= H; b += 256) {
+        double2 z = make_double2(0.0, 0.0);
+        if (b == 0) z = make_double2(P[0].x, 0.0);
+        else if (b <= L) z = P[b];
+        if (b > 0 && N - b <= L) z = cadd(z, cconj(P[N - b]));
+        X[b] = z;
+    }
+    __syncthreads();
+    // pack: F_k = (X_k + conj X_{H-k}) + i W^k (X_k - conj X_{H-k}), k in [0, H)
+    for (int k = tid; 2 * k <= H; k += 256) {
+        const double2 a = X[k], b = X[H - k];
+        const double2 s1 = cadd(a, cconj(b)), d1 = cmul(tw[k], csub(a, cconj(b)));
+        const double2 f1 = make_double2(s1.x - d1.y, s1.y + d1.x);
+        if (k > 0 && 2 * k < H) {
+            const double2 s2 = cadd(b, cconj(a)), d2 = cmul(tw[H - k], csub(b, cconj(a)));
+            X[H - k] = make_double2(s2.x - d2.y, s2.y + d2.x);
+        }
+        X[k] = f1;
+    }
+    __syncthreads();
+    int Ns = 1, rem = H;
+    while (rem >= 16) { stockham_pass<16>(X, H, Ns, N, tw); Ns *= 16; rem /= 16; }
+    if (rem == 8) stockham_pass<8>(X, H, Ns, N, tw);
+    else if (rem == 4) stockham_pass<4>(X, H, Ns, N, tw);
+    else if (rem == 2) stockham_pass<2>(X, H, Ns, N, tw);
+    // f_n = c[2n] + i c[2n+1]
+    double2* out = reinterpret_cast<double2*>(c.cube) + ((size_t)c.ring0 * c.nalpha + row) * (size_t)H;
+    for (int n = tid; n < H; n += 256) out[n] = X[n];
+}
+
+}  // namespace
+
+int launch_cube(const CubeArgs& c, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = 2 * c.mbmax + 1;
+    const size_t sh1 = sizeof(double2) * ((size_t)c.nalpha * nb + (size_t)CA_Q * CA_T * (CA_T + 1));
+    dim3 g1((c.nring_chunk + CA_T - 1) / CA_T, (c.lmax + 1 + CA_T - 1) / CA_T);
+    if (c.nalpha <= 8)
+        hipLaunchKernelGGL(k_cube_alpha<8>, g1, dim3(256), sh1, s, c);
+    else if (c.nalpha <= 16)
+        hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), sh1, s, c);
+    else
+        hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), sh1, s, c);
+    int rc = (int)hipGetLastError();
+    if (rc) return rc;
+    const size_t sh2 = sizeof(double2) * ((size_t)c.ngamma / 2 + 1);
+    hipLaunchKernelGGL(k_cube_gamma, dim3(c.nring_chunk * c.nalpha), dim3(256), sh2, s, c);
+    return (int)hipGetLastError();
+}
+
+int cube_set_lds_limits()
+{
+    // the gamma pass needs up to (8192 + 1) * 16 bytes of LDS, the alpha pass up to 99 KB
+    int rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (CG_HMAX + 1) * (int)sizeof(double2));
+    const int a_max = (4096 + CA_Q * CA_T * (CA_T + 1)) * (int)sizeof(double2);
+    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<8>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<16>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<32>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    return rc;
+}
+
+}  // namespace tc

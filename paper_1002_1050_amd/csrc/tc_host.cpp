@@ -58,8 +58,8 @@ void split_dd(ld v, double& hi, double& lo)
 
 // ---------------------------------------------------------------- tile choice
 
-constexpr int kNumOps = 4;   // TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL
-tc::Tile g_tile_override[kNumOps] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // 0 = built-in
+constexpr int kNumOps = 5;   // TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE
+tc::Tile g_tile_override[kNumOps] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // 0 = built-in
 
 tc::Tile default_tile(int op, int lmax)
 {
@@ -84,7 +84,7 @@ tc::Tile default_tile(int op, int lmax)
 struct KernelTiming {
     int cap = 0;
     std::vector<hipEvent_t> start[kNumOps], stop[kNumOps];
-    long long recorded[kNumOps] = {0, 0, 0, 0};
+    long long recorded[kNumOps] = {0, 0, 0, 0, 0};
 };
 KernelTiming g_timing;
 
@@ -389,7 +389,114 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
     return TC_OK;
 }
 
+// ---------------------------------------------------------------- data cube
+
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+constexpr size_t kCubeChunkBytes = (size_t)1 << 31;   // alpha sums held per ring chunk
+
+struct CubeLayout {
+    size_t phase = 0, tw = 0, P = 0, total = 0;
+    int chunk = 0;
+};
+
+CubeLayout make_cube_layout(int lmax, int mbmax, int nring, int nalpha, int ngamma)
+{
+    CubeLayout C;
+    const size_t per_ring = (size_t)16 * (size_t)nalpha * (size_t)(lmax + 1);
+    C.chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nring, kCubeChunkBytes / per_ring));
+    size_t off = 0;
+    C.phase = off; off = align_up(off + (size_t)16 * nalpha * (2 * mbmax + 1));
+    C.tw = off;    off = align_up(off + (size_t)16 * ngamma);
+    C.P = off;     off = align_up(off + per_ring * (size_t)C.chunk);
+    C.total = off;
+    return C;
+}
+
+int check_cube(int lmax, int mbmax, int nring, int nalpha, int ngamma)
+{
+    if (lmax < 0 || lmax > 8192) return fail(TC_EINVAL, "data cube: lmax = %d outside [0, 8192]", lmax);
+    if (mbmax < 0 || mbmax > lmax) return fail(TC_EINVAL, "data cube: mbmax = %d outside [0, lmax]", mbmax);
+    if (nring < 1) return fail(TC_EINVAL, "data cube: nring must be >= 1");
+    if (nalpha < 1 || (long long)nalpha * (2 * mbmax + 1) > 4096)
+        return fail(TC_EINVAL, "data cube: nalpha = %d must be >= 1 with nalpha*(2*mbmax+1) <= 4096", nalpha);
+    if (ngamma < 2 || ngamma > 16384 || (ngamma & (ngamma - 1)) || ngamma < 2 * lmax)
+        return fail(TC_EINVAL, "data cube: ngamma = %d must be a power of two in [max(2, 2*lmax), 16384]", ngamma);
+    return TC_OK;
+}
+
 }  // namespace
+
+extern "C" {
+
+size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int nalpha, int ngamma)
+{
+    const std::string saved = g_error;
+    const int rc = check_cube(lmax, mbmax, nring, nalpha, ngamma);
+    g_error = saved;
+    return rc ? 0 : make_cube_layout(lmax, mbmax, nring, nalpha, ngamma).total;
+}
+
+int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma, double* cube,
+                       void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    int rc = check_cube(lmax, mbmax, nring, nalpha, ngamma);
+    if (rc) return rc;
+    if (!C || !cube) return fail(TC_EINVAL, "C or cube is NULL");
+    if (!aligned16(C) || !aligned16(cube)) return fail(TC_EINVAL, "C and cube must be 16-byte aligned");
+    const CubeLayout CL = make_cube_layout(lmax, mbmax, nring, nalpha, ngamma);
+    if (ws_bytes < CL.total)
+        return fail(TC_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, CL.total);
+    if (!workspace) return fail(TC_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(TC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    int dev = 0, lds_max = 0;
+    if ((rc = (int)hipGetDevice(&dev)) ||
+        (rc = (int)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)))
+        return hip_fail(rc, "data cube: device query");
+    (void)tc::cube_set_lds_limits();   // opt-in beyond 64 KB where the runtime asks for it
+    const size_t need = std::max((size_t)16 * (ngamma / 2 + 1),
+                                 (size_t)16 * ((size_t)nalpha * (2 * mbmax + 1) + 8 * 16 * 17));
+    if (need > (size_t)lds_max)
+        return fail(TC_EUNSUPPORTED, "data cube needs %zu bytes of LDS per workgroup, the device allows %d", need,
+                    lds_max);
+    // tables: e^{-2 pi i mb a / nalpha} and e^{-2 pi i m / ngamma}, in long double, rounded once
+    std::vector<char> img(CL.P, 0);
+    double* ph = reinterpret_cast<double*>(img.data() + CL.phase);
+    const int nb = 2 * mbmax + 1;
+    for (int a = 0; a < nalpha; ++a)
+        for (int mb = -mbmax; mb <= mbmax; ++mb) {
+            const long long m = (((long long)mb * a) % nalpha + nalpha) % nalpha;
+            const ld ang = 2.0L * kPiL * (ld)m / (ld)nalpha;
+            ph[2 * (a * nb + mb + mbmax)] = (double)cosl(ang);
+            ph[2 * (a * nb + mb + mbmax) + 1] = (double)-sinl(ang);
+        }
+    double* tw = reinterpret_cast<double*>(img.data() + CL.tw);
+    for (int m = 0; m < ngamma; ++m) {
+        const ld ang = 2.0L * kPiL * (ld)m / (ld)ngamma;
+        tw[2 * m] = (double)cosl(ang);
+        tw[2 * m + 1] = (double)-sinl(ang);
+    }
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::CubeArgs c{};
+    c.lmax = lmax; c.mbmax = mbmax; c.nring = nring; c.nalpha = nalpha; c.ngamma = ngamma;
+    c.C = C;
+    c.phase = reinterpret_cast<const double*>(static_cast<char*>(workspace) + CL.phase);
+    c.tw = reinterpret_cast<const double*>(static_cast<char*>(workspace) + CL.tw);
+    c.P = reinterpret_cast<double*>(static_cast<char*>(workspace) + CL.P);
+    c.cube = cube;
+    for (int r0 = 0; r0 < nring; r0 += CL.chunk) {
+        c.ring0 = r0;
+        c.nring_chunk = std::min(CL.chunk, nring - r0);
+        if ((long long)c.nring_chunk * nalpha > 0x7fffffffLL)
+            return fail(TC_EUNSUPPORTED, "data cube: too many rows in one launch");
+        rc = timed_launch(TC_OP_CUBE, stream, [&] { return tc::launch_cube(c, stream); });
+        if (rc) return hip_fail(rc, "totalconv_datacube launch");
+    }
+    return TC_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

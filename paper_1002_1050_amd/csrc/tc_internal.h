@@ -78,6 +78,21 @@ struct EpiArgs {
     double* blm_bar;       // may be null
 };
 
+// Data cube (eq. conviqt) of rings [ring0, ring0 + nring_chunk).
+struct CubeArgs {
+    int lmax, mbmax, nring, nalpha, ngamma;
+    int ring0, nring_chunk;
+    const double* C;       // [2M+1][L+1][nring] complex (totalconv_fwd output)
+    const double* phase;   // [nalpha][2M+1] complex, e^{-2 pi i mb a / nalpha}
+    const double* tw;      // [ngamma] complex, e^{-2 pi i m / ngamma}
+    double* P;             // [nring_chunk][nalpha][L+1] complex, alpha sums
+    double* cube;          // [nring][nalpha][ngamma] real
+};
+
+// Data-cube launchers (tc_cube.hip).
+int launch_cube(const CubeArgs& c, void* stream);
+int cube_set_lds_limits();
+
 // Kernel launchers (tc_kernels.hip).  Return a hipError_t value (0 on success).
 int launch_wigner(const WignerArgs& a, Tile t, void* stream);
 int launch_fwd(const FwdArgs& a, Tile t, void* stream);

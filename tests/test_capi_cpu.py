@@ -112,7 +112,8 @@ def test_timing_arguments_checked_on_host(L):
     buf = (ctypes.c_float * 4)()
     assert L.tc_timing_enable(-1) == -1
     assert L.tc_timing_enable(65537) == -1
-    assert L.tc_timing_read(4, buf, 4) == -1
+    assert L.tc_timing_read(5, buf, 4) == -1
+    assert L.tc_timing_read(-1, buf, 4) == -1
     assert L.tc_timing_read(1, None, 4) == -1
     assert L.tc_timing_read(1, buf, 4) == 0          # timing off: nothing recorded
     assert L.tc_timing_enable(0) == 0
@@ -138,3 +139,21 @@ def test_polarised_arguments_checked_on_host(L):
     # summed mode needs one cotangent only; nothing requested is a no-op
     one = (ctypes.c_void_p * 1)(fake[0])
     assert L.totalconv_adj_pol(10, 2, x.size, xp, 3, arr, arr, 1, one, None, None, ws, 1 << 30, None) == 0
+
+
+def test_datacube_arguments_checked_on_host(L):
+    from paper_1002_1050_amd import _binding as B
+    fake = ctypes.c_void_p(0x200000)
+    ws = ctypes.c_void_p(0x100000)
+    ok = dict(lmax=10, mbmax=2, nring=4, nalpha=5, ngamma=32)
+    assert L.totalconv_datacube_workspace_bytes(*ok.values()) > 0
+    bad = [dict(ok, ngamma=24), dict(ok, ngamma=16), dict(ok, ngamma=32768), dict(ok, nalpha=0),
+           dict(ok, nalpha=900), dict(ok, mbmax=11), dict(ok, lmax=8193, ngamma=16384), dict(ok, nring=0)]
+    for b in bad:
+        assert L.totalconv_datacube_workspace_bytes(*b.values()) == 0, b
+        rc = L.totalconv_datacube(b["lmax"], b["mbmax"], b["nring"], fake, b["nalpha"], b["ngamma"], fake, ws,
+                                  1 << 40, None)
+        assert rc == -1, b
+    assert L.totalconv_datacube(10, 2, 4, fake, 5, 32, fake, ws, 16, None) == -3
+    assert L.totalconv_datacube(10, 2, 4, ctypes.c_void_p(0x200008), 5, 32, fake, ws, 1 << 40, None) == -1
+    assert "aligned" in B.last_error()
