@@ -414,7 +414,7 @@ def main():
         "roofline": roofline,
         "tiles_R_TB_TR": tiles,
     }
-    if args.cube_reps > 0 and not args.fwd_only:
+    if args.cube_reps > 0:
         log("data cube")
         result["datacube"] = datacube_timing(w, C, args.cube_reps)
     if args.cpu_seconds > 0:

@@ -192,7 +192,7 @@ int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int
  *                phase and twiddle tables and the alpha sums of one ring chunk
  *                (at most 2 GiB; rings are processed in chunks)
  * TC_EUNSUPPORTED if the device allows less LDS per workgroup than the FFT of
- * length ngamma needs (8 * ngamma + 16 bytes).
+ * length ngamma needs (8.5 * ngamma + 16 bytes).
  */
 size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int nalpha, int ngamma);
 int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma,

@@ -8,7 +8,7 @@
 // that c is real.
 //
 // Two passes, both bound by HBM bandwidth:
-//  1. k_cube_alpha: P[j][a][k] = sum_mb E[a][mb] C[mb][k][j] for k = msky >= 0 -- the
+//  1. k_cube_alpha: P[j][a][k] = sum_mb E[mb][a] C[mb][k][j] for k = msky >= 0 -- the
 //     short sum over mb, done directly with the host's phase table E, and the
 //     transpose from ring-fastest C to rows (ring, alpha) with msky fastest.
 //  2. k_cube_gamma: one workgroup per row turns P_0..P_L into the real row
@@ -38,22 +38,26 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 constexpr int CA_T = 16;    // rings and msky values per workgroup tile (16 x 16 = 256 lanes)
 constexpr int CA_Q = 8;     // alpha values per transposed store
 
+// Each lane owns one (msky, ring) element and sums its 2M+1 values of C against the
+// phases of QA values of alpha.  The C values are loaded CA_U at a time (all in flight
+// together); the phase table [mb][alpha] sits in LDS and is read as broadcasts.
+constexpr int CA_U = 8;
+
 template <int QA>
-__global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c)
+__global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c, const double2* __restrict__ C,
+                                                    const double2* __restrict__ Eg, double2* __restrict__ P)
 {
-    extern __shared__ double2 sh[];
+    __shared__ double2 tile[CA_Q][CA_T][CA_T + 1];
+    extern __shared__ double2 E[];   // [nb][nalpha]
     const int nb = 2 * c.mbmax + 1;
-    double2* E = sh;                                 // [nalpha][nb]
-    double2* tile = sh + c.nalpha * nb;              // [CA_Q][CA_T][CA_T + 1]
     const int tid = threadIdx.x;
-    for (int i = tid; i < c.nalpha * nb; i += 256) E[i] = reinterpret_cast<const double2*>(c.phase)[i];
+    for (int i = tid; i < nb * c.nalpha; i += 256) E[i] = Eg[i];
     const int jj = tid & (CA_T - 1), kk = tid / CA_T;
     const int j0 = blockIdx.x * CA_T, k0 = blockIdx.y * CA_T;
     const int j = j0 + jj, k = k0 + kk;
     const int L1 = c.lmax + 1;
     const bool in = (j < c.nring_chunk) && (k <= c.lmax);
-    const double2* C = reinterpret_cast<const double2*>(c.C);
-    double2* P = reinterpret_cast<double2*>(c.P);
+    const size_t mb_stride = (size_t)L1 * c.nring;
     __syncthreads();
     for (int a0 = 0; a0 < c.nalpha; a0 += QA) {
         double ar[QA], ai[QA];
@@ -61,14 +65,23 @@ __global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c)
         for (int q = 0; q < QA; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
         if (in) {
             const double2* src = C + (size_t)k * c.nring + (c.ring0 + j);
-            for (int mb = 0; mb < nb; ++mb) {
-                const double2 v = src[(size_t)mb * L1 * c.nring];
+            for (int mb0 = 0; mb0 < nb; mb0 += CA_U) {
+                double2 v[CA_U];
 #pragma unroll
-                for (int q = 0; q < QA; ++q) {
-                    if (a0 + q < c.nalpha) {
-                        const double2 e = E[(a0 + q) * nb + mb];
-                        ar[q] = fma(e.x, v.x, fma(-e.y, v.y, ar[q]));
-                        ai[q] = fma(e.x, v.y, fma(e.y, v.x, ai[q]));
+                for (int u = 0; u < CA_U; ++u)
+                    v[u] = (mb0 + u < nb) ? src[(size_t)(mb0 + u) * mb_stride] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < CA_U; ++u) {
+                    if (mb0 + u < nb) {
+                        const double2* e_row = E + (mb0 + u) * c.nalpha + a0;
+#pragma unroll
+                        for (int q = 0; q < QA; ++q) {
+                            if (a0 + q < c.nalpha) {
+                                const double2 e = e_row[q];
+                                ar[q] = fma(e.x, v[u].x, fma(-e.y, v[u].y, ar[q]));
+                                ai[q] = fma(e.x, v[u].y, fma(e.y, v[u].x, ai[q]));
+                            }
+                        }
                     }
                 }
             }
@@ -78,14 +91,12 @@ __global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c)
         for (int q0 = 0; q0 < QA; q0 += CA_Q) {
             if (a0 + q0 >= c.nalpha) break;
 #pragma unroll
-            for (int q = 0; q < CA_Q; ++q)
-                tile[(q * CA_T + kk) * (CA_T + 1) + jj] = make_double2(ar[q0 + q], ai[q0 + q]);
+            for (int q = 0; q < CA_Q; ++q) tile[q][kk][jj] = make_double2(ar[q0 + q], ai[q0 + q]);
             __syncthreads();
             const int jw = tid / CA_T, kw = tid & (CA_T - 1);
             if (j0 + jw < c.nring_chunk && k0 + kw <= c.lmax) {
                 for (int q = 0; q < CA_Q && a0 + q0 + q < c.nalpha; ++q)
-                    P[((size_t)(j0 + jw) * c.nalpha + (a0 + q0 + q)) * L1 + (k0 + kw)] =
-                        tile[(q * CA_T + kw) * (CA_T + 1) + jw];
+                    P[((size_t)(j0 + jw) * c.nalpha + (a0 + q0 + q)) * L1 + (k0 + kw)] = tile[q][kw][jw];
             }
             __syncthreads();
         }
@@ -144,20 +155,66 @@ __device__ __forceinline__ void dft_regs(double2 (&v)[R])
 
 constexpr int CG_HMAX = 8192;   // largest half length (ngamma <= 16384)
 
-// One Stockham pass of radix R over X[0..H) in place (all reads, barrier, all writes).
+// LDS slot of element i: one pad slot per 16 elements, so that the first pass's
+// stride-16 stores (and every other pass's accesses) spread over the banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// Twiddles w_r = W^{r m1} for r < R from W^{m1}, W^{2 m1}, W^{4 m1}, W^{8 m1} of the
+// host table: every w_r is a table entry or a product of at most three of them.
 template <int R>
+__device__ __forceinline__ void twiddle_base(const double2* __restrict__ tw, int m1, double2 (&b)[4])
+{
+    b[0] = tw[m1];
+    if (R > 2) b[1] = tw[2 * m1];
+    if (R > 4) b[2] = tw[4 * m1];
+    if (R > 8) b[3] = tw[8 * m1];
+}
+
+template <int R>
+__device__ __forceinline__ void apply_twiddles(double2 (&v)[R], const double2 (&b)[4])
+{
+    double2 w[R];
+    w[1] = b[0];
+    if (R > 2) { w[2] = b[1]; w[3] = cmul(b[0], b[1]); }
+    if (R > 4) {
+        w[4] = b[2];
+#pragma unroll
+        for (int r = 5; r < 8; ++r) w[r] = cmul(b[2], w[r - 4]);
+    }
+    if (R > 8) {
+        w[8] = b[3];
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(b[3], w[r - 8]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+}
+
+// One Stockham pass of radix R over X[0..H) in place (all reads, barrier, all writes);
+// HMAX bounds H, hence the groups a lane handles.
+template <int R, int HMAX>
 __device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, const double2* __restrict__ tw)
 {
-    constexpr int GM = CG_HMAX / (R * 256);
+    constexpr int GM = HMAX / (R * 256) > 0 ? HMAX / (R * 256) : 1;
     const int tid = threadIdx.x;
     const int ng = H / R;
-    double2 v[GM][R];
+    const int step = N / (Ns * R);
+    double2 v[GM][R], b[GM][4];
+    // twiddle loads first (their latency overlaps the LDS reads and the barrier);
+    // the first pass (Ns = 1) has only unit twiddles
+    if (Ns > 1) {
+#pragma unroll
+        for (int i = 0; i < GM; ++i) {
+            const int g = tid + 256 * i;
+            if (g < ng) twiddle_base<R>(tw, (g & (Ns - 1)) * step, b[i]);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < GM; ++i) {
         const int g = tid + 256 * i;
         if (g < ng) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = X[g + r * ng];
+            for (int r = 0; r < R; ++r) v[i][r] = X[pad(g + r * ng)];
         }
     }
     __syncthreads();
@@ -166,21 +223,20 @@ __device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, 
         const int g = tid + 256 * i;
         if (g < ng) {
             const int k = g & (Ns - 1);
-            const int step = N / (Ns * R);
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[k * r * step]);
+            if (Ns > 1) apply_twiddles<R>(v[i], b[i]);
             dft_regs<R>(v[i]);
             const int base = (g - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) X[base + r * Ns] = v[i][r];
+            for (int r = 0; r < R; ++r) X[pad(base + r * Ns)] = v[i][r];
         }
     }
     __syncthreads();
 }
 
+template <int HMAX>
 __global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
 {
-    extern __shared__ double2 X[];   // H + 1 entries
+    extern __shared__ double2 X[];   // pad(H) + 1 entries
     const int row = blockIdx.x;      // (ring within the chunk) * nalpha + alpha
     const int N = c.ngamma, H = N / 2, L = c.lmax;
     const int tid = threadIdx.x;
@@ -192,29 +248,29 @@ __global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
         if (b == 0) z = make_double2(P[0].x, 0.0);
         else if (b <= L) z = P[b];
         if (b > 0 && N - b <= L) z = cadd(z, cconj(P[N - b]));
-        X[b] = z;
+        X[pad(b)] = z;
     }
     __syncthreads();
     // pack: F_k = (X_k + conj X_{H-k}) + i W^k (X_k - conj X_{H-k}), k in [0, H)
     for (int k = tid; 2 * k <= H; k += 256) {
-        const double2 a = X[k], b = X[H - k];
+        const double2 a = X[pad(k)], b = X[pad(H - k)];
         const double2 s1 = cadd(a, cconj(b)), d1 = cmul(tw[k], csub(a, cconj(b)));
         const double2 f1 = make_double2(s1.x - d1.y, s1.y + d1.x);
         if (k > 0 && 2 * k < H) {
             const double2 s2 = cadd(b, cconj(a)), d2 = cmul(tw[H - k], csub(b, cconj(a)));
-            X[H - k] = make_double2(s2.x - d2.y, s2.y + d2.x);
+            X[pad(H - k)] = make_double2(s2.x - d2.y, s2.y + d2.x);
         }
-        X[k] = f1;
+        X[pad(k)] = f1;
     }
     __syncthreads();
     int Ns = 1, rem = H;
-    while (rem >= 16) { stockham_pass<16>(X, H, Ns, N, tw); Ns *= 16; rem /= 16; }
-    if (rem == 8) stockham_pass<8>(X, H, Ns, N, tw);
-    else if (rem == 4) stockham_pass<4>(X, H, Ns, N, tw);
-    else if (rem == 2) stockham_pass<2>(X, H, Ns, N, tw);
+    while (rem >= 16) { stockham_pass<16, HMAX>(X, H, Ns, N, tw); Ns *= 16; rem /= 16; }
+    if (rem == 8) stockham_pass<8, HMAX>(X, H, Ns, N, tw);
+    else if (rem == 4) stockham_pass<4, HMAX>(X, H, Ns, N, tw);
+    else if (rem == 2) stockham_pass<2, HMAX>(X, H, Ns, N, tw);
     // f_n = c[2n] + i c[2n+1]
     double2* out = reinterpret_cast<double2*>(c.cube) + ((size_t)c.ring0 * c.nalpha + row) * (size_t)H;
-    for (int n = tid; n < H; n += 256) out[n] = X[n];
+    for (int n = tid; n < H; n += 256) out[n] = X[pad(n)];
 }
 
 }  // namespace
@@ -222,31 +278,42 @@ __global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
 int launch_cube(const CubeArgs& c, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    const int nb = 2 * c.mbmax + 1;
-    const size_t sh1 = sizeof(double2) * ((size_t)c.nalpha * nb + (size_t)CA_Q * CA_T * (CA_T + 1));
     dim3 g1((c.nring_chunk + CA_T - 1) / CA_T, (c.lmax + 1 + CA_T - 1) / CA_T);
+    const double2* C = reinterpret_cast<const double2*>(c.C);
+    const double2* E = reinterpret_cast<const double2*>(c.phase);
+    double2* P = reinterpret_cast<double2*>(c.P);
+    const size_t sh1 = sizeof(double2) * (size_t)c.nalpha * (2 * c.mbmax + 1);
     if (c.nalpha <= 8)
-        hipLaunchKernelGGL(k_cube_alpha<8>, g1, dim3(256), sh1, s, c);
+        hipLaunchKernelGGL(k_cube_alpha<8>, g1, dim3(256), sh1, s, c, C, E, P);
     else if (c.nalpha <= 16)
-        hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), sh1, s, c);
+        hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), sh1, s, c, C, E, P);
     else
-        hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), sh1, s, c);
+        hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), sh1, s, c, C, E, P);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
-    const size_t sh2 = sizeof(double2) * ((size_t)c.ngamma / 2 + 1);
-    hipLaunchKernelGGL(k_cube_gamma, dim3(c.nring_chunk * c.nalpha), dim3(256), sh2, s, c);
+    const int H = c.ngamma / 2;
+    const size_t sh2 = sizeof(double2) * ((size_t)H + (H >> 4) + 1);
+    if (H <= 4096)
+        hipLaunchKernelGGL(k_cube_gamma<4096>, dim3(c.nring_chunk * c.nalpha), dim3(256), sh2, s, c);
+    else
+        hipLaunchKernelGGL(k_cube_gamma<CG_HMAX>, dim3(c.nring_chunk * c.nalpha), dim3(256), sh2, s, c);
     return (int)hipGetLastError();
 }
 
 int cube_set_lds_limits()
 {
-    // the gamma pass needs up to (8192 + 1) * 16 bytes of LDS, the alpha pass up to 99 KB
-    int rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (CG_HMAX + 1) * (int)sizeof(double2));
-    const int a_max = (4096 + CA_Q * CA_T * (CA_T + 1)) * (int)sizeof(double2);
-    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<8>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
-    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<16>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
-    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_alpha<32>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    // the gamma pass needs up to (8192 + 512 + 1) * 16 bytes of LDS
+    // the alpha pass: the phase table, at most 4096 entries, beside its 34 KB tile
+    int rc = 0;
+    const int a_max = 4096 * (int)sizeof(double2);
+    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<8>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<16>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<32>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
+    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma<4096>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (4096 + 4096 / 16 + 1) * (int)sizeof(double2));
+    if (!rc)
+        rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma<CG_HMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (CG_HMAX + CG_HMAX / 16 + 1) * (int)sizeof(double2));
     return rc;
 }
 

@@ -455,12 +455,13 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
         (rc = (int)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)))
         return hip_fail(rc, "data cube: device query");
     (void)tc::cube_set_lds_limits();   // opt-in beyond 64 KB where the runtime asks for it
-    const size_t need = std::max((size_t)16 * (ngamma / 2 + 1),
+    // LDS per workgroup: the FFT row (padded), or the alpha pass's phase table and its 34 KB tile
+    const size_t need = std::max((size_t)16 * (ngamma / 2 + ngamma / 32 + 1),
                                  (size_t)16 * ((size_t)nalpha * (2 * mbmax + 1) + 8 * 16 * 17));
     if (need > (size_t)lds_max)
         return fail(TC_EUNSUPPORTED, "data cube needs %zu bytes of LDS per workgroup, the device allows %d", need,
                     lds_max);
-    // tables: e^{-2 pi i mb a / nalpha} and e^{-2 pi i m / ngamma}, in long double, rounded once
+    // tables: e^{-2 pi i mb a / nalpha} ([mb][a]) and e^{-2 pi i m / ngamma}, in long double, rounded once
     std::vector<char> img(CL.P, 0);
     double* ph = reinterpret_cast<double*>(img.data() + CL.phase);
     const int nb = 2 * mbmax + 1;
@@ -468,8 +469,8 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
         for (int mb = -mbmax; mb <= mbmax; ++mb) {
             const long long m = (((long long)mb * a) % nalpha + nalpha) % nalpha;
             const ld ang = 2.0L * kPiL * (ld)m / (ld)nalpha;
-            ph[2 * (a * nb + mb + mbmax)] = (double)cosl(ang);
-            ph[2 * (a * nb + mb + mbmax) + 1] = (double)-sinl(ang);
+            ph[2 * ((size_t)(mb + mbmax) * nalpha + a)] = (double)cosl(ang);
+            ph[2 * ((size_t)(mb + mbmax) * nalpha + a) + 1] = (double)-sinl(ang);
         }
     double* tw = reinterpret_cast<double*>(img.data() + CL.tw);
     for (int m = 0; m < ngamma; ++m) {

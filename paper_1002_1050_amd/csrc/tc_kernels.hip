@@ -165,13 +165,31 @@ __device__ __forceinline__ void recursion_coefs(int l, int mb, int ms, int lmax,
     F2 = (l1 * (sqrt(ll * ll - b2) * sqrt(ll * ll - s2))) / (ll * den);
 }
 
-// Exact power-of-two rescale of one chain (and the values tied to it).
+// Binary exponent e of max(|d|, |d_prev|) (|v| in [2^(e-1), 2^e)); a zero value does
+// not count (the caller treats d = d_prev = 0 as the zero chain).
 __device__ __forceinline__ int chain_exponent(double d, double dp)
 {
     int e1, e2;
     frexp(d, &e1);
     frexp(dp, &e2);
-    return max(e1, e2);
+    constexpr int NONE = -(1 << 20);
+    return max(d != 0.0 ? e1 : NONE, dp != 0.0 ? e2 : NONE);
+}
+
+// For plain chains (E = 0) the skip test of check_chain reduces to a threshold:
+// max(|d|, |d_prev|) >= 2^(-skip_exp - GROWTH_BITS_PER_STEP * TS).
+template <int R>
+__device__ __forceinline__ bool lane_may_be_hot(const double (&d)[R], const double (&dp)[R], double thr)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) m = fmax(m, fmax(fabs(d[r]), fabs(dp[r])));
+    return m >= thr;
+}
+
+__device__ __forceinline__ double hot_threshold(int skip_exp)
+{
+    return ldexp(1.0, -skip_exp - GROWTH_BITS_PER_STEP * TS);
 }
 
 // One scale / skip check of a chain, every TS steps.  From the exponent e of
@@ -424,6 +442,7 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
     bool acc_on = (a.skip_exp <= 0);
+    const double thr = hot_threshold(a.skip_exp);
 
     const int st = stage_slot<NT, TB>(tid);
     RawW raw[NP];
@@ -443,13 +462,13 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
             for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, lb + TB + st, mb, ms);
         }
         for (int s0 = 0; s0 < TB; s0 += TS) {
-            if (scaled || !acc_on) {
+            if (scaled) {
                 bool any = false, hot = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     int k;
-                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, scaled, k);
-                    if (scaled && acc_on) {   // sums in the chain's scaled units follow it
+                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
+                    if (acc_on) {   // sums in the chain's scaled units follow it
 #pragma unroll
                         for (int c = 0; c < NC; ++c) {
                             c1r[c][r] = ldexp(c1r[c][r], k); c1i[c][r] = ldexp(c1i[c][r], k);
@@ -458,8 +477,10 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
                     }
                     any |= (E[r] < 0);
                 }
-                if (scaled) scaled = wave_any(any);
+                scaled = wave_any(any);
                 if (!acc_on) acc_on = wave_any(hot);
+            } else if (!acc_on) {
+                acc_on = wave_any(lane_may_be_hot<R>(d, dp, thr));
             }
             if (acc_on)
                 fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
@@ -618,6 +639,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
     bool acc_on = (a.skip_exp <= 0);    // wave-uniform
+    const double thr = hot_threshold(a.skip_exp);
 
     double2* U = reinterpret_cast<double2*>(a.U) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
@@ -635,18 +657,20 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
         for (int s0 = 0; s0 < TB; s0 += TS) {
-            if (scaled || !acc_on) {
+            if (scaled) {
                 bool any = false, hot = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const bool was = E[r] < 0;
                     int k;
-                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, scaled, k);
+                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
                     if (was && E[r] == 0) load_g(r);
                     any |= (E[r] < 0);
                 }
-                if (scaled) scaled = wave_any(any);
+                scaled = wave_any(any);
                 if (!acc_on) acc_on = wave_any(hot);
+            } else if (!acc_on) {
+                acc_on = wave_any(lane_may_be_hot<R>(d, dp, thr));
             }
             if (acc_on) {
                 for (int h = 0; h < TS; h += TR) {
