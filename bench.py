@@ -70,6 +70,8 @@ def parse():
                    help="timed repetitions of the polarised forward (three pairs, separate and summed; 0 skips)")
     p.add_argument("--cube-reps", type=int, default=2,
                    help="timed repetitions of the data-cube stage on the forward's output (0 skips)")
+    p.add_argument("--matrix-reps", type=int, default=2,
+                   help="timed repetitions of the full-matrix generator at l = lmax on 16 rings (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
     p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB' (skips its autotuning)")
@@ -226,6 +228,34 @@ def datacube_timing(w, C, reps):
     return {"workload": f"data cube, nalpha={na}, ngamma={ng}, {w.nring} rings, lmax={w.lmax}, mbmax={w.mbmax}",
             "kernel_ms": round(kms, 3), "call_ms": round(wall * 1e3, 3), "algorithmic_bytes": nbytes,
             "hbm_gb_per_s": nbytes / (kms * 1e-3) / 1e9, "ring_chunks": len(chunks) // reps}
+
+
+def matrix_timing(w, reps, nring=16):
+    """Full matrix d^l_{m m'}, -l <= m, m' <= l, at l = lmax on nring seeded rings.
+    The output is written once: 8 bytes per element, the kernel's algorithmic HBM traffic."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import synthetic as S
+    l = w.lmax
+    x = S.ring_cosines(2 * nring + 1)[1:nring + 1]
+    out = torch.empty((nring, 2 * l + 1, 2 * l + 1), dtype=torch.float64, device="cuda:0")
+    B.wigner_d_matrix(l, x, out=out)   # warm-up
+    torch.cuda.synchronize()
+    B.timing_enable(reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.wigner_d_matrix(l, x, out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    kms = float(np.mean(B.timing_read(B.TC_OP_MATRIX, reps)))
+    B.timing_enable(0)
+    n = out.numel()
+    del out
+    torch.cuda.empty_cache()
+    log(f"  full matrix l={l}: kernel {kms:.2f} ms, {n / (kms * 1e-3):.3e} elements/s, {8 * n / (kms * 1e-3) / 1e9:.0f} GB/s")
+    return {"workload": f"full Wigner matrix at l={l}, {nring} rings", "elements": n, "kernel_ms": round(kms, 3),
+            "call_ms": round(wall * 1e3, 3), "elements_per_s": n / (kms * 1e-3),
+            "hbm_gb_per_s": 8 * n / (kms * 1e-3) / 1e9}
 
 
 def polarised_compare(w, x, alm, blm, reps, tune):
@@ -417,6 +447,9 @@ def main():
     if args.cube_reps > 0:
         log("data cube")
         result["datacube"] = datacube_timing(w, C, args.cube_reps)
+    if args.matrix_reps > 0:
+        log("full matrix")
+        result["matrix"] = matrix_timing(w, args.matrix_reps)
     if args.cpu_seconds > 0:
         nring = w.nring
         Gc = G.reshape(-1, nring)

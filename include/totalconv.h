@@ -58,6 +58,7 @@ extern "C" {
 #define TC_OP_ADJ 2
 #define TC_OP_FWD_POL 3       /* tiles / workspace of totalconv_fwd_pol */
 #define TC_OP_CUBE 4          /* timing of totalconv_datacube */
+#define TC_OP_MATRIX 5        /* tiles / timing of wigner_d_matrix */
 
 #define TC_POL_SEPARATE 0     /* polarised: one output per (sky, beam) pair */
 #define TC_POL_SUM 1          /* polarised: one output, the sum over the pairs */
@@ -103,6 +104,25 @@ size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, c
 int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky,
                    int nring, const double* cosbeta, double* d,
                    void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * The full reduced Wigner matrix at one l (Sec. 3.1): d^l_{m m'}(beta_j) for
+ * -l <= m, m' <= l, without the elements of any other l.  Each row of fixed m is
+ * walked in m' with the three-term relation of Sec. 2 (eq. mrec), downwards from
+ * its closed-form end point d^l_{m,l} (Sec. 3.2 seed, as a logarithm, with exact
+ * power-of-two scaling), over 0 <= m <= m' <= l at beta and at pi - beta; the
+ * other elements follow from the symmetries of the appendix.  This is the
+ * recursion that the ratio form of Sec. 3.1 writes as ratios of neighbours.
+ *   l            0 <= l <= TC_LMAX_LIMIT
+ *   nring >= 1;  cosbeta (host) nring ring cosines in [-1, 1] (the poles included)
+ *   d            out: [nring][2l+1][2l+1] doubles, d[j][m+l][m'+l] = d^l_{m m'}(beta_j);
+ *                values below the double range come out as 0 or subnormal
+ *   workspace    at least wigner_d_matrix_workspace_bytes(l, nring) bytes
+ * tc_set_tile(TC_OP_MATRIX, R) picks R in {1, 2} rows per lane (0: built-in).
+ */
+size_t wigner_d_matrix_workspace_bytes(int l, int nring);
+int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d,
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Total-convolution coefficients (Sec. 4.1, eq. convdef):
@@ -269,7 +289,7 @@ int tc_plan_destroy(void* plan);
  * totalconv_fwd_pol call records one pair (under op TC_OP_WIGNER, TC_OP_FWD,
  * TC_OP_ADJ, TC_OP_FWD_POL) on its own stream, directly before and after its
  * recursion kernel; totalconv_datacube records one TC_OP_CUBE pair around the
- * two kernels of each ring chunk (for the adjoint: without the two short epilogue kernels
+ * two kernels of each ring chunk, wigner_d_matrix one TC_OP_MATRIX pair (for the adjoint: without the two short epilogue kernels
  * that finish the gradients; totalconv_adj_pol records one TC_OP_ADJ pair per
  * cotangent), reusing the pairs cyclically.  n = 0 releases the events and
  * stops the recording.  Calls must then run on streams of that device.

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtotalconv.so")
 
-TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE = 0, 1, 2, 3, 4
+TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE, TC_OP_MATRIX = 0, 1, 2, 3, 4, 5
 TC_POL_SEPARATE, TC_POL_SUM = 0, 1
 TC_LMAX_LIMIT = 16384
 
@@ -86,6 +86,10 @@ def lib():
             L.totalconv_fwd_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, P, S, P]
             L.totalconv_adj_pol.restype = I
             L.totalconv_adj_pol.argtypes = [I, I, I, P, I, PP, PP, I, PP, PP, PP, P, S, P]
+            L.wigner_d_matrix_workspace_bytes.restype = S
+            L.wigner_d_matrix_workspace_bytes.argtypes = [I, I]
+            L.wigner_d_matrix.restype = I
+            L.wigner_d_matrix.argtypes = [I, I, P, P, P, S, P]
             L.totalconv_datacube_workspace_bytes.restype = S
             L.totalconv_datacube_workspace_bytes.argtypes = [I, I, I, I, I]
             L.totalconv_datacube.restype = I
@@ -177,6 +181,26 @@ def wigner_d_rings(lmax: int, mb, msky, cosbeta, device="cuda"):
     rc = lib().wigner_d_rings(lmax, mb.size, _hptr(mb), _hptr(ms), x.size, _hptr(x), _dptr(out),
                               _dptr(ws), ws.numel(), stream)
     _check("wigner_d_rings", rc)
+    return out
+
+
+def wigner_d_matrix(l: int, cosbeta, device="cuda", out=None):
+    """Full matrix d^l_{m m'}(beta_j), -l <= m, m' <= l: float64 (nring, 2l+1, 2l+1) on the GPU."""
+    import torch
+    device = torch.device(device)
+    x = _host(np.atleast_1d(cosbeta), np.float64)
+    shape = (x.size, 2 * l + 1, 2 * l + 1)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=device)
+    else:
+        _require_device(out, "out", torch.float64)
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {shape}")
+        device = out.device
+    stream = _stream_handle(torch, device)
+    ws = workspace_cache.get(torch, device, stream, int(lib().wigner_d_matrix_workspace_bytes(l, max(x.size, 1))))
+    rc = lib().wigner_d_matrix(l, x.size, _hptr(x), _dptr(out), _dptr(ws), ws.numel(), stream)
+    _check("wigner_d_matrix", rc)
     return out
 
 

@@ -58,8 +58,10 @@ void split_dd(ld v, double& hi, double& lo)
 
 // ---------------------------------------------------------------- tile choice
 
-constexpr int kNumOps = 5;   // TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE
-tc::Tile g_tile_override[kNumOps] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // 0 = built-in
+constexpr int kNumOps = 6;   // TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE, TC_OP_MATRIX
+tc::Tile g_tile_override[kNumOps] = {{0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}, {0, 256, 0, 0}};   // 0 = built-in
+
+int g_matrix_R = 0;   // rows per lane of wigner_d_matrix (tc_set_tile); 0 = built-in
 
 tc::Tile default_tile(int op, int lmax)
 {
@@ -84,7 +86,7 @@ tc::Tile default_tile(int op, int lmax)
 struct KernelTiming {
     int cap = 0;
     std::vector<hipEvent_t> start[kNumOps], stop[kNumOps];
-    long long recorded[kNumOps] = {0, 0, 0, 0, 0};
+    long long recorded[kNumOps] = {0, 0, 0, 0, 0, 0};
 };
 KernelTiming g_timing;
 
@@ -389,6 +391,23 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
     return TC_OK;
 }
 
+// ------------------------------------------------------------- full matrix
+
+struct MatrixLayout {
+    size_t ring = 0, trig = 0, lna = 0, total = 0;
+};
+
+MatrixLayout make_matrix_layout(int l, int nring)
+{
+    MatrixLayout M;
+    size_t off = 0;
+    M.ring = off; off = align_up(off + sizeof(double) * 5 * (size_t)nring);
+    M.trig = off; off = align_up(off + sizeof(double) * 2 * (size_t)nring);
+    M.lna = off;  off = align_up(off + sizeof(double) * 2 * (size_t)(l + 1));
+    M.total = off;
+    return M;
+}
+
 // ---------------------------------------------------------------- data cube
 
 constexpr long double kPiL = 3.14159265358979323846264338327950288L;
@@ -428,6 +447,58 @@ int check_cube(int lmax, int mbmax, int nring, int nalpha, int ngamma)
 
 extern "C" {
 
+size_t wigner_d_matrix_workspace_bytes(int l, int nring)
+{
+    if (l < 0 || l > TC_LMAX_LIMIT || nring < 1) return 0;
+    return make_matrix_layout(l, nring).total;
+}
+
+int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d, void* workspace, size_t ws_bytes,
+                    void* stream)
+{
+    g_error.clear();
+    if (l < 0 || l > TC_LMAX_LIMIT) return fail(TC_EINVAL, "l = %d outside [0, %d]", l, TC_LMAX_LIMIT);
+    int rc = check_rings(nring, cosbeta);
+    if (rc) return rc;
+    if (!d) return fail(TC_EINVAL, "d is NULL");
+    if (reinterpret_cast<uintptr_t>(d) % 8) return fail(TC_EINVAL, "d must be 8-byte aligned");
+    const MatrixLayout M = make_matrix_layout(l, nring);
+    if (ws_bytes < M.total)
+        return fail(TC_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, M.total);
+    if (!workspace) return fail(TC_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(TC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    const int R = g_matrix_R > 0 ? g_matrix_R : 1;
+    const int ntile = (l + 1 + 64 * R - 1) / (64 * R);   // one-wave workgroups of R rows per lane
+    if ((long long)ntile * 2 * nring > 0x7fffffffLL)
+        return fail(TC_EUNSUPPORTED, "launch of %lld workgroups exceeds the grid limit", (long long)ntile * 2 * nring);
+    std::vector<char> img(M.total, 0);
+    Layout RL;
+    RL.ring = M.ring;
+    build_rings(nring, cosbeta, img, RL);
+    double* trig = reinterpret_cast<double*>(img.data() + M.trig);
+    for (int j = 0; j < nring; ++j) {   // cot and csc of beta from x in long double
+        const ld X = (ld)cosbeta[j];
+        const ld sn = sqrtl((1.0L - X) * (1.0L + X));
+        trig[2 * j] = sn > 0 ? (double)(X / sn) : 0.0;
+        trig[2 * j + 1] = sn > 0 ? (double)(1.0L / sn) : 0.0;
+    }
+    double* lna = reinterpret_cast<double*>(img.data() + M.lna);
+    for (int m = 0; m <= l; ++m) {      // ln sqrt((2l)! / ((l+m)! (l-m)!))
+        const ld v = 0.5L * (lgammal((ld)(2 * l + 1)) - lgammal((ld)(l + m + 1)) - lgammal((ld)(l - m + 1)));
+        split_dd(v, lna[2 * m], lna[2 * m + 1]);
+    }
+    if ((rc = upload(workspace, img, stream))) return rc;
+    tc::MatrixArgs a{};
+    a.l = l; a.nring = nring; a.ntile = ntile;
+    a.ring = ring_ptrs(workspace, RL, nring);
+    a.trig = reinterpret_cast<const double*>(static_cast<char*>(workspace) + M.trig);
+    a.lnA = reinterpret_cast<const double*>(static_cast<char*>(workspace) + M.lna);
+    a.d = d;
+    rc = timed_launch(TC_OP_MATRIX, stream, [&] { return tc::launch_matrix(a, R, stream); });
+    return rc ? hip_fail(rc, "wigner_d_matrix launch") : TC_OK;
+}
+
 size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int nalpha, int ngamma)
 {
     const std::string saved = g_error;
@@ -464,7 +535,6 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
     // tables: e^{-2 pi i mb a / nalpha} ([mb][a]) and e^{-2 pi i m / ngamma}, in long double, rounded once
     std::vector<char> img(CL.P, 0);
     double* ph = reinterpret_cast<double*>(img.data() + CL.phase);
-    const int nb = 2 * mbmax + 1;
     for (int a = 0; a < nalpha; ++a)
         for (int mb = -mbmax; mb <= mbmax; ++mb) {
             const long long m = (((long long)mb * a) % nalpha + nalpha) % nalpha;
@@ -507,6 +577,12 @@ int tc_set_tile_ex(int op, int R, int TB, int TR)
 {
     if (op < 0 || op >= kNumOps) return fail(TC_EINVAL, "tc_set_tile: unknown op %d", op);
     if (R < 0 || TB < 0 || TR < 0) return fail(TC_EINVAL, "tc_set_tile: negative tile parameter");
+    if (op == TC_OP_MATRIX) {
+        if (R > 2 || (TB && TB != 32) || (TR && TR != 4))
+            return fail(TC_EINVAL, "tc_set_tile: (R %d, TB %d, TR %d) is not built for op %d", R, TB, TR, op);
+        g_matrix_R = R;
+        return TC_OK;
+    }
     const tc::Tile o = g_tile_override[op];
     g_tile_override[op] = tc::Tile{R, 256, TB, TR};
     if (!tc::tile_supported(op, default_tile(op, 1 << 20))) {
@@ -526,6 +602,7 @@ int tc_set_tile(int op, int R)
 int tc_get_tile(int op, int lmax)
 {
     if (op < 0 || op >= kNumOps) return 0;
+    if (op == TC_OP_MATRIX) return g_matrix_R > 0 ? g_matrix_R : 1;
     return default_tile(op, lmax).R;
 }
 
@@ -533,8 +610,8 @@ int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR)
 {
     if (op < 0 || op >= kNumOps || !R || !TB || !TR) return fail(TC_EINVAL, "tc_get_tile_ex: bad arguments");
     const tc::Tile t = default_tile(op, lmax);
-    *R = t.R;
-    *TB = t.TB;
+    *R = op == TC_OP_MATRIX ? (g_matrix_R > 0 ? g_matrix_R : 1) : t.R;
+    *TB = op == TC_OP_MATRIX ? 32 : t.TB;
     *TR = t.TR;
     return TC_OK;
 }

@@ -78,6 +78,18 @@ struct EpiArgs {
     double* blm_bar;       // may be null
 };
 
+// Full matrix d^l_{m m'} at one l: the m' recursion on the triangle 0 <= m <= m' <= l
+// at beta (side 0) and at pi - beta (side 1), written out with its symmetric images.
+struct MatrixArgs {
+    int l, nring, ntile;   // ntile: row tiles per (ring, side)
+    RingTables ring;       // x, ln cos(beta/2), ln sin(beta/2)
+    const double* trig;    // [nring][2]: cot(beta), csc(beta) (unused at the poles)
+    const double* lnA;     // [l+1][2] double-double ln sqrt((2l)! / ((l+m)! (l-m)!))
+    double* d;             // [nring][2l+1][2l+1], d[j][m+l][m'+l]
+};
+
+int launch_matrix(const MatrixArgs& a, int R, void* stream);
+
 // Data cube (eq. conviqt) of rings [ring0, ring0 + nring_chunk).
 struct CubeArgs {
     int lmax, mbmax, nring, nalpha, ngamma;

@@ -112,7 +112,7 @@ def test_timing_arguments_checked_on_host(L):
     buf = (ctypes.c_float * 4)()
     assert L.tc_timing_enable(-1) == -1
     assert L.tc_timing_enable(65537) == -1
-    assert L.tc_timing_read(5, buf, 4) == -1
+    assert L.tc_timing_read(6, buf, 4) == -1
     assert L.tc_timing_read(-1, buf, 4) == -1
     assert L.tc_timing_read(1, None, 4) == -1
     assert L.tc_timing_read(1, buf, 4) == 0          # timing off: nothing recorded
@@ -157,3 +157,23 @@ def test_datacube_arguments_checked_on_host(L):
     assert L.totalconv_datacube(10, 2, 4, fake, 5, 32, fake, ws, 16, None) == -3
     assert L.totalconv_datacube(10, 2, 4, ctypes.c_void_p(0x200008), 5, 32, fake, ws, 1 << 40, None) == -1
     assert "aligned" in B.last_error()
+
+
+def test_matrix_arguments_checked_on_host(L):
+    from paper_1002_1050_amd import _binding as B
+    x = np.array([0.3, 0.1])
+    xp = x.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x200000)
+    ws = ctypes.c_void_p(0x100000)
+    assert L.wigner_d_matrix_workspace_bytes(10, 2) > 0
+    assert L.wigner_d_matrix_workspace_bytes(-1, 2) == 0 and L.wigner_d_matrix_workspace_bytes(10, 0) == 0
+    assert L.wigner_d_matrix(-1, 2, xp, fake, ws, 1 << 30, None) == -1
+    assert L.wigner_d_matrix(16385, 2, xp, fake, ws, 1 << 30, None) == -1
+    assert L.wigner_d_matrix(10, 2, xp, None, ws, 1 << 30, None) == -1
+    assert L.wigner_d_matrix(10, 2, xp, ctypes.c_void_p(0x200004), ws, 1 << 30, None) == -1
+    assert L.wigner_d_matrix(10, 2, xp, fake, ws, 16, None) == -3
+    bad = np.array([0.3, 1.5])
+    assert L.wigner_d_matrix(10, 2, bad.ctypes.data_as(ctypes.c_void_p), fake, ws, 1 << 30, None) == -1
+    assert "cosbeta" in B.last_error()
+    assert L.tc_set_tile(5, 3) == -1 and L.tc_set_tile(5, 2) == 0 and L.tc_get_tile(5, 10) == 2
+    assert L.tc_set_tile(5, 0) == 0 and L.tc_get_tile(5, 10) == 1 and L.tc_get_tile(5, 2000) == 1
