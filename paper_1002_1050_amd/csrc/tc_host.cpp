@@ -418,11 +418,14 @@ struct CubeLayout {
     int chunk = 0;
 };
 
+int g_cube_chunk = 0;   // rings per chunk of the data cube (tc_set_tile); 0 = built-in
+
 CubeLayout make_cube_layout(int lmax, int mbmax, int nring, int nalpha, int ngamma)
 {
     CubeLayout C;
     const size_t per_ring = (size_t)16 * (size_t)nalpha * (size_t)(lmax + 1);
     C.chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nring, kCubeChunkBytes / per_ring));
+    if (g_cube_chunk > 0) C.chunk = std::min(C.chunk, g_cube_chunk);
     size_t off = 0;
     C.phase = off; off = align_up(off + (size_t)16 * nalpha * (2 * mbmax + 1));
     C.tw = off;    off = align_up(off + (size_t)16 * ngamma);
@@ -583,6 +586,11 @@ int tc_set_tile_ex(int op, int R, int TB, int TR)
         g_matrix_R = R;
         return TC_OK;
     }
+    if (op == TC_OP_CUBE) {   // R: largest ring chunk of the data cube
+        if (TB || TR) return fail(TC_EINVAL, "tc_set_tile: the data cube takes a ring chunk only");
+        g_cube_chunk = R;
+        return TC_OK;
+    }
     const tc::Tile o = g_tile_override[op];
     g_tile_override[op] = tc::Tile{R, 256, TB, TR};
     if (!tc::tile_supported(op, default_tile(op, 1 << 20))) {
@@ -602,6 +610,7 @@ int tc_set_tile(int op, int R)
 int tc_get_tile(int op, int lmax)
 {
     if (op < 0 || op >= kNumOps) return 0;
+    if (op == TC_OP_CUBE) return g_cube_chunk;
     if (op == TC_OP_MATRIX) return g_matrix_R > 0 ? g_matrix_R : 1;
     return default_tile(op, lmax).R;
 }

@@ -41,10 +41,10 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 template <int R>
 constexpr int min_waves() { return R >= 8 ? 2 : (R >= 4 ? 3 : 4); }
 
-// Polarised forward: NC outputs carry 4 NC sums per chain and the staging lanes hold
-// NP pairs of raw weights, so the budget is one step lower than the scalar kernel's.
+// Polarised forward: NC > 1 outputs carry 4 NC sums per chain, so their budget is one
+// step lower than the scalar kernel's; the summed output (NC = 1) keeps the scalar one.
 template <int R, int NC, int NP>
-constexpr int fwd_min_waves() { return (NC == 1 && NP == 1) ? min_waves<R>() : (R >= 4 ? 2 : 3); }
+constexpr int fwd_min_waves() { return NC == 1 ? min_waves<R>() : (R >= 4 ? 2 : 3); }
 
 // The adjoint's LDS (about 53 KB per workgroup with TB = 32, 62 KB with TB = 64)
 // caps residency at 3 or 2 workgroups (waves per SIMD) per CU.

@@ -177,3 +177,11 @@ def test_matrix_arguments_checked_on_host(L):
     assert "cosbeta" in B.last_error()
     assert L.tc_set_tile(5, 3) == -1 and L.tc_set_tile(5, 2) == 0 and L.tc_get_tile(5, 10) == 2
     assert L.tc_set_tile(5, 0) == 0 and L.tc_get_tile(5, 10) == 1 and L.tc_get_tile(5, 2000) == 1
+
+
+def test_cube_chunk_setting(L):
+    full = L.totalconv_datacube_workspace_bytes(20, 3, 17, 7, 64)
+    assert L.tc_set_tile(4, 3) == 0 and L.tc_get_tile(4, 0) == 3
+    assert L.totalconv_datacube_workspace_bytes(20, 3, 17, 7, 64) < full
+    assert L.tc_set_tile_ex(4, 3, 32, 0) == -1
+    assert L.tc_set_tile(4, 0) == 0 and L.totalconv_datacube_workspace_bytes(20, 3, 17, 7, 64) == full

@@ -96,3 +96,20 @@ def test_cube_rejects_bad_grids(B):
             B.totalconv_datacube(10, 2, C, Na, Ng)      # ngamma not a power of two >= 2 lmax, ...
     with pytest.raises(B.TotalConvError, match="nalpha"):
         B.totalconv_datacube(10, 2, C, 900, 32)        # nalpha * (2 mbmax + 1) > 4096
+
+
+def test_cube_ring_chunks_give_the_same_cube(B):
+    """Rings processed in chunks (here 3 at a time, 6 chunks) give the unchunked cube bit for bit."""
+    L, M, n, Na, Ng = 20, 3, 17, 7, 64
+    C = torch.from_numpy(random_C(L, M, n, 77)).cuda()
+    whole = B.totalconv_datacube(L, M, C, Na, Ng).clone()
+    B.set_tile(B.TC_OP_CUBE, 3)
+    try:
+        B.timing_enable(16)
+        chunked = B.totalconv_datacube(L, M, C, Na, Ng)
+        torch.cuda.synchronize()
+        assert len(B.timing_read(B.TC_OP_CUBE, 16)) == 6
+    finally:
+        B.timing_enable(0)
+        B.set_tile(B.TC_OP_CUBE, 0)
+    assert torch.equal(whole, chunked)
