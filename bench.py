@@ -36,11 +36,14 @@ FLOPS_PER_TERM_UNPAIRED = 9.0
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "207ccca218aaa066c07d995ae5525436a6f6e691cf4aa4c20a250d818b8d6820",
+    "kernel_source_sha256": "962eb5dfc2db86d47e008330e845b35ef6f71af66e80ab693defefd5720a3d0d",
     "lmax4096": {
-        # FETCH_SIZE KiB x 1024 x 2.000 + WRITE_SIZE KiB x 1024 x 1.000 (2 GiB copy calibration)
-        "k_fwd": int(564556.25 * 1024 * 2.0 + 15208064.0 * 1024),
-        "k_adj": int(5937291.0 * 1024 * 2.0 + 15227844.3125 * 1024),
+        # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
+        #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
+        "k_fwd": int(564943.5625 * 1024 * (2147483648 / (1048611.6875 * 1024))
+                     + 15208064.0 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5953501.25 * 1024 * (2147483648 / (1048611.6875 * 1024))
+                     + 15228082.46875 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
