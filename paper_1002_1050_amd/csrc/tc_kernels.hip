@@ -216,16 +216,16 @@ __device__ __forceinline__ bool check_chain(double& d, double& dp, int& E, int s
     return nz & (te + GROWTH_BITS_PER_STEP * TS > -skip_exp);
 }
 
-// Which l offset in a TB block this lane stages, or -1.  The TB values are spread
-// over the workgroup's waves (TB / (NT/64) lanes per wave) so that no wave carries
-// the staging work alone.
+// Which l offset of TB block `blk` this lane stages, or -1.  One wave stages a whole
+// block, so that its square roots and divisions keep all lanes busy, and the duty
+// rotates over the workgroup's waves from block to block.
 template <int NT, int TB>
-__device__ __forceinline__ int stage_slot(int tid)
+__device__ __forceinline__ int stage_slot(int tid, int blk)
 {
-    constexpr int per_wave = TB / (NT / 64);
-    static_assert(per_wave >= 1 && per_wave <= 64 && TB % (NT / 64) == 0, "staging split");
+    static_assert(TB <= 64, "one wave stages a block");
+    constexpr int NW = NT / 64;
     const int lane = tid & 63;
-    return lane < per_wave ? (tid >> 6) * per_wave + lane : -1;
+    return ((tid >> 6) == blk % NW && lane < TB) ? lane : -1;
 }
 
 __device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
@@ -266,11 +266,11 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
 
-    const int st = stage_slot<NT, TB>(tid);
-    if (st >= 0) {
+    const int st0 = stage_slot<NT, TB>(tid, 0);
+    if (st0 >= 0) {
         double A, nB, F2;
-        recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
-        cf[0][st] = make_double4(A, nB, F2, 0.0);
+        recursion_coefs(l0 + st0, mb, ms, L, A, nB, F2);
+        cf[0][st0] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -303,6 +303,7 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
                 }
             }
         }
+        const int st = stage_slot<NT, TB>(tid, kb + 1);
         if (st >= 0 && kb + 1 < nblk) {
             double A, nB, F2;
             recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
@@ -444,18 +445,19 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     bool acc_on = (a.skip_exp <= 0);
     const double thr = hot_threshold(a.skip_exp);
 
-    const int st = stage_slot<NT, TB>(tid);
     RawW raw[NP];
-    if (st >= 0) {
+    const int st0 = stage_slot<NT, TB>(tid, 0);
+    if (st0 >= 0) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, l0 + st, mb, ms);
-        stage_block<NC, NP>(a, raw, l0 + st, mb, ms, cf[0][st]);
+        for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, l0 + st0, mb, ms);
+        stage_block<NC, NP>(a, raw, l0 + st0, mb, ms, cf[0][st0]);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
     for (int kb = 0; kb < nblk; ++kb) {
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
+        const int st = stage_slot<NT, TB>(tid, kb + 1);
         const bool stage = (st >= 0) && (kb + 1 < nblk);
         if (stage) {   // in flight during the block
 #pragma unroll
@@ -645,11 +647,11 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
 
-    const int st = stage_slot<NT, TB>(tid);
-    if (st >= 0) {
+    const int st0 = stage_slot<NT, TB>(tid, 0);
+    if (st0 >= 0) {
         double A, nB, F2;
-        recursion_coefs(l0 + st, mb, ms, L, A, nB, F2);
-        sh_.cf[0][st] = make_double4(A, nB, F2, 0.0);
+        recursion_coefs(l0 + st0, mb, ms, L, A, nB, F2);
+        sh_.cf[0][st0] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -729,6 +731,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
             }
         }
+        const int st = stage_slot<NT, TB>(tid, kb + 1);
         if (st >= 0 && kb + 1 < nblk) {
             double A, nB, F2;
             recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
