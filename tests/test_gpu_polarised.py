@@ -132,3 +132,50 @@ def test_polarised_rejects_bad_arguments(B):
     rc = lib.totalconv_fwd_pol(L, M, x.size, xp, 3, arr(da[:2] + [None]), arr(db), 0, arr(out),
                                B._dptr(ws), ws.numel(), None)
     assert rc == -1 and "pair 2" in B.last_error()
+
+
+@pytest.mark.parametrize("summed", [False, True])
+def test_polarised_autograd_central_differences(B, summed):
+    """TotalConvPol's backward (the polarised adjoint) against central differences of a quadratic
+    loss, for every pair's sky and beam."""
+    from paper_1002_1050_amd.autograd import TotalConvPol
+    L, M, n = 20, 2, 41
+    x = S.ring_cosines(n)
+    mode = B.TC_POL_SUM if summed else B.TC_POL_SEPARATE
+    alms = [dev(S.sky_alm(L, 60 + p) + 0.0j).requires_grad_(True) for p in range(3)]
+    blms = [dev(S.random_beam(L, M, 70 + p)).requires_grad_(True) for p in range(3)]
+    Ts = [dev(S.random_cbar(L, M, n, 80 + k)) for k in range(1 if summed else 3)]
+    say(f"polarised autograd, summed={summed}")
+
+    def loss(a_list, b_list):
+        outs = TotalConvPol.apply(mode, x, L, M, *a_list, *b_list)
+        return 0.5 * sum(torch.sum(torch.abs(C - T) ** 2) for C, T in zip(outs, Ts))
+
+    loss(alms, blms).backward()
+    grads = [t.grad.clone() for t in alms + blms]
+    gmax = max(g.abs().max().item() for g in grads)
+    rng = np.random.Generator(np.random.PCG64(11))
+    h = 1e-3
+    with torch.no_grad():
+        for p in range(3):
+            for k in rng.choice(alms[p].numel(), 4, replace=False):
+                for unit in (1.0, 1j):
+                    d = torch.zeros_like(alms[p])
+                    d[k] = h * unit
+                    plus = [a + d if q == p else a for q, a in enumerate(alms)]
+                    minus = [a - d if q == p else a for q, a in enumerate(alms)]
+                    fd = ((loss(plus, blms) - loss(minus, blms)) / (2 * h)).item()
+                    g = grads[p][k]
+                    assert abs(fd - (g.real.item() if unit == 1.0 else g.imag.item())) <= 1e-8 * gmax
+            for _ in range(4):
+                r, l = int(rng.integers(0, 2 * M + 1)), int(rng.integers(0, L + 1))
+                if l < abs(r - M):
+                    continue
+                for unit in (1.0, 1j):
+                    d = torch.zeros_like(blms[p])
+                    d[r, l] = h * unit
+                    plus = [b + d if q == p else b for q, b in enumerate(blms)]
+                    minus = [b - d if q == p else b for q, b in enumerate(blms)]
+                    fd = ((loss(alms, plus) - loss(alms, minus)) / (2 * h)).item()
+                    g = grads[3 + p][r, l]
+                    assert abs(fd - (g.real.item() if unit == 1.0 else g.imag.item())) <= 1e-8 * gmax
