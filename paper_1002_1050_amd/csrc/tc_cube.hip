@@ -9,7 +9,8 @@
 //
 // Two passes, both bound by HBM bandwidth:
 //  1. k_cube_alpha: P[j][a][k] = sum_mb E[mb][a] C[mb][k][j] for k = msky >= 0 -- the
-//     short sum over mb, done directly with the host's phase table E, and the
+//     short sum over mb, done directly with the host's phase table E (read into scalar
+//     registers, four phases per load), and the
 //     transpose from ring-fastest C to rows (ring, alpha) with msky fastest.
 //  2. k_cube_gamma: one workgroup per row turns P_0..P_L into the real row
 //     c[g] = Re P_0 + 2 Re sum_{k>=1} P_k e^{-2 pi i k g / N}: the Hermitian
@@ -40,25 +41,30 @@ constexpr int CA_Q = 8;     // alpha values per transposed store
 
 // Each lane owns one (msky, ring) element and sums its 2M+1 values of C against the
 // phases of QA values of alpha.  The C values are loaded CA_U at a time (all in flight
-// together); the phase table [mb][alpha] sits in LDS and is read as broadcasts.
+// together).  The phase table [mb][alpha] (alpha padded to a multiple of 4) is read with
+// uniform 64-byte loads, four phases at a time, so the phases arrive in scalar registers
+// and every C value feeds 4 QA fused multiply-adds without LDS traffic.
 constexpr int CA_U = 8;
+
+struct alignas(64) Phase4 {
+    double2 v[4];
+};
 
 template <int QA>
 __global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c, const double2* __restrict__ C,
-                                                    const double2* __restrict__ Eg, double2* __restrict__ P)
+                                                    const Phase4* __restrict__ E4, double2* __restrict__ P)
 {
+    static_assert(QA % 4 == 0, "phases come in fours");
     __shared__ double2 tile[CA_Q][CA_T][CA_T + 1];
-    extern __shared__ double2 E[];   // [nb][nalpha]
     const int nb = 2 * c.mbmax + 1;
+    const int na4 = (c.nalpha + 3) / 4;     // Phase4 entries per mb row
     const int tid = threadIdx.x;
-    for (int i = tid; i < nb * c.nalpha; i += 256) E[i] = Eg[i];
     const int jj = tid & (CA_T - 1), kk = tid / CA_T;
     const int j0 = blockIdx.x * CA_T, k0 = blockIdx.y * CA_T;
     const int j = j0 + jj, k = k0 + kk;
     const int L1 = c.lmax + 1;
     const bool in = (j < c.nring_chunk) && (k <= c.lmax);
     const size_t mb_stride = (size_t)L1 * c.nring;
-    __syncthreads();
     for (int a0 = 0; a0 < c.nalpha; a0 += QA) {
         double ar[QA], ai[QA];
 #pragma unroll
@@ -73,13 +79,17 @@ __global__ void __launch_bounds__(256) k_cube_alpha(const CubeArgs c, const doub
 #pragma unroll
                 for (int u = 0; u < CA_U; ++u) {
                     if (mb0 + u < nb) {
-                        const double2* e_row = E + (mb0 + u) * c.nalpha + a0;
+                        const Phase4* row = E4 + (size_t)(mb0 + u) * na4 + a0 / 4;
 #pragma unroll
-                        for (int q = 0; q < QA; ++q) {
-                            if (a0 + q < c.nalpha) {
-                                const double2 e = e_row[q];
-                                ar[q] = fma(e.x, v[u].x, fma(-e.y, v[u].y, ar[q]));
-                                ai[q] = fma(e.x, v[u].y, fma(e.y, v[u].x, ai[q]));
+                        for (int q4 = 0; q4 < QA / 4; ++q4) {
+                            if (a0 + 4 * q4 < c.nalpha) {
+                                const Phase4 e = row[q4];
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    const int q = 4 * q4 + i;
+                                    ar[q] = fma(e.v[i].x, v[u].x, fma(-e.v[i].y, v[u].y, ar[q]));
+                                    ai[q] = fma(e.v[i].x, v[u].y, fma(e.v[i].y, v[u].x, ai[q]));
+                                }
                             }
                         }
                     }
@@ -280,15 +290,14 @@ int launch_cube(const CubeArgs& c, void* stream)
     hipStream_t s = (hipStream_t)stream;
     dim3 g1((c.nring_chunk + CA_T - 1) / CA_T, (c.lmax + 1 + CA_T - 1) / CA_T);
     const double2* C = reinterpret_cast<const double2*>(c.C);
-    const double2* E = reinterpret_cast<const double2*>(c.phase);
+    const Phase4* E = reinterpret_cast<const Phase4*>(c.phase);
     double2* P = reinterpret_cast<double2*>(c.P);
-    const size_t sh1 = sizeof(double2) * (size_t)c.nalpha * (2 * c.mbmax + 1);
     if (c.nalpha <= 8)
-        hipLaunchKernelGGL(k_cube_alpha<8>, g1, dim3(256), sh1, s, c, C, E, P);
+        hipLaunchKernelGGL(k_cube_alpha<8>, g1, dim3(256), 0, s, c, C, E, P);
     else if (c.nalpha <= 16)
-        hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), sh1, s, c, C, E, P);
+        hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), 0, s, c, C, E, P);
     else
-        hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), sh1, s, c, C, E, P);
+        hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), 0, s, c, C, E, P);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     const int H = c.ngamma / 2;
@@ -303,13 +312,7 @@ int launch_cube(const CubeArgs& c, void* stream)
 int cube_set_lds_limits()
 {
     // the gamma pass needs up to (8192 + 512 + 1) * 16 bytes of LDS
-    // the alpha pass: the phase table, at most 4096 entries, beside its 34 KB tile
-    int rc = 0;
-    const int a_max = 4096 * (int)sizeof(double2);
-    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<8>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
-    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<16>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
-    rc |= (int)hipFuncSetAttribute((const void*)k_cube_alpha<32>, hipFuncAttributeMaxDynamicSharedMemorySize, a_max);
-    if (!rc) rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma<4096>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    int rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma<4096>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (4096 + 4096 / 16 + 1) * (int)sizeof(double2));
     if (!rc)
         rc = (int)hipFuncSetAttribute((const void*)k_cube_gamma<CG_HMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,

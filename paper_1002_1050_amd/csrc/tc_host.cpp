@@ -427,7 +427,7 @@ CubeLayout make_cube_layout(int lmax, int mbmax, int nring, int nalpha, int ngam
     C.chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nring, kCubeChunkBytes / per_ring));
     if (g_cube_chunk > 0) C.chunk = std::min(C.chunk, g_cube_chunk);
     size_t off = 0;
-    C.phase = off; off = align_up(off + (size_t)16 * nalpha * (2 * mbmax + 1));
+    C.phase = off; off = align_up(off + (size_t)16 * ((nalpha + 3) / 4 * 4) * (2 * mbmax + 1));
     C.tw = off;    off = align_up(off + (size_t)16 * ngamma);
     C.P = off;     off = align_up(off + per_ring * (size_t)C.chunk);
     C.total = off;
@@ -529,21 +529,21 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
         (rc = (int)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)))
         return hip_fail(rc, "data cube: device query");
     (void)tc::cube_set_lds_limits();   // opt-in beyond 64 KB where the runtime asks for it
-    // LDS per workgroup: the FFT row (padded), or the alpha pass's phase table and its 34 KB tile
-    const size_t need = std::max((size_t)16 * (ngamma / 2 + ngamma / 32 + 1),
-                                 (size_t)16 * ((size_t)nalpha * (2 * mbmax + 1) + 8 * 16 * 17));
+    // LDS per workgroup: the FFT row (padded); the alpha pass uses a fixed 34 KB tile
+    const size_t need = (size_t)16 * (ngamma / 2 + ngamma / 32 + 1);
     if (need > (size_t)lds_max)
         return fail(TC_EUNSUPPORTED, "data cube needs %zu bytes of LDS per workgroup, the device allows %d", need,
                     lds_max);
     // tables: e^{-2 pi i mb a / nalpha} ([mb][a]) and e^{-2 pi i m / ngamma}, in long double, rounded once
     std::vector<char> img(CL.P, 0);
     double* ph = reinterpret_cast<double*>(img.data() + CL.phase);
+    const size_t na4 = (size_t)(nalpha + 3) / 4 * 4;   // rows padded to whole groups of 4 (zeros)
     for (int a = 0; a < nalpha; ++a)
         for (int mb = -mbmax; mb <= mbmax; ++mb) {
             const long long m = (((long long)mb * a) % nalpha + nalpha) % nalpha;
             const ld ang = 2.0L * kPiL * (ld)m / (ld)nalpha;
-            ph[2 * ((size_t)(mb + mbmax) * nalpha + a)] = (double)cosl(ang);
-            ph[2 * ((size_t)(mb + mbmax) * nalpha + a) + 1] = (double)-sinl(ang);
+            ph[2 * ((size_t)(mb + mbmax) * na4 + a)] = (double)cosl(ang);
+            ph[2 * ((size_t)(mb + mbmax) * na4 + a) + 1] = (double)-sinl(ang);
         }
     double* tw = reinterpret_cast<double*>(img.data() + CL.tw);
     for (int m = 0; m < ngamma; ++m) {

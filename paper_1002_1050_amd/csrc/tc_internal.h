@@ -95,7 +95,7 @@ struct CubeArgs {
     int lmax, mbmax, nring, nalpha, ngamma;
     int ring0, nring_chunk;
     const double* C;       // [2M+1][L+1][nring] complex (totalconv_fwd output)
-    const double* phase;   // [2M+1][nalpha] complex, e^{-2 pi i mb a / nalpha}
+    const double* phase;   // [2M+1][nalpha rounded up to 4] complex, e^{-2 pi i mb a / nalpha} (pad: 0)
     const double* tw;      // [ngamma] complex, e^{-2 pi i m / ngamma}
     double* P;             // [nring_chunk][nalpha][L+1] complex, alpha sums
     double* cube;          // [nring][nalpha][ngamma] real
