@@ -200,24 +200,82 @@ __device__ __forceinline__ void apply_twiddles(double2 (&v)[R], const double2 (&
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
 }
 
-// One Stockham pass of radix R over X[0..H) in place (all reads, barrier, all writes);
-// HMAX bounds H, hence the groups a lane handles.
+// Entry b in [0, H] of the half spectrum: X_b = Z_b + Z_{b-N} with Z_0 = Re P_0,
+// Z_k = P_k and Z_{-k} = conj(P_k) for 1 <= k <= L (zero beyond L).
+__device__ __forceinline__ double2 half_spec(const double2* __restrict__ P, int b, int N, int L)
+{
+    double2 z = make_double2(0.0, 0.0);
+    if (b == 0) z = make_double2(P[0].x, 0.0);
+    else if (b <= L) z = P[b];
+    if (b > 0 && N - b <= L) z = cadd(z, cconj(P[N - b]));
+    return z;
+}
+
+// Packed input of the half-length transform: F_k = (X_k + conj X_{H-k}) + i W^k (X_k - conj X_{H-k}).
+__device__ __forceinline__ double2 packed(double2 a, double2 b, double2 w)
+{
+    const double2 s = cadd(a, cconj(b)), d = cmul(w, csub(a, cconj(b)));
+    return make_double2(s.x - d.y, s.y + d.x);
+}
+
+// First Stockham pass (stride Ns = 1, unit twiddles), fed straight from HBM: lane g
+// forms F_{g + r H/R} for r < R from the row of P and transforms them in registers.
+// All of a lane's loads are issued before the first is used.  The result goes to LDS,
+// or, when this is the only pass, to the output row.
 template <int R, int HMAX>
-__device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, const double2* __restrict__ tw)
+__device__ __forceinline__ void first_pass(const double2* __restrict__ P, const double2* __restrict__ tw,
+                                           int H, int N, int L, double2* X, double2* out, bool last)
+{
+    constexpr int GM = HMAX / (R * 256) > 0 ? HMAX / (R * 256) : 1;
+    const int tid = threadIdx.x;
+    const int ng = H / R;
+    double2 v[GM][R];
+#pragma unroll
+    for (int i = 0; i < GM; ++i) {
+        const int g = tid + 256 * i;
+        if (g < ng) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = g + r * ng;
+                v[i][r] = packed(half_spec(P, k, N, L), half_spec(P, H - k, N, L), tw[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < GM; ++i) {
+        const int g = tid + 256 * i;
+        if (g < ng) {
+            dft_regs<R>(v[i]);
+            if (last) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) out[g * R + r] = v[i][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) X[pad(g * R + r)] = v[i][r];
+            }
+        }
+    }
+    if (!last) __syncthreads();
+}
+
+// One later Stockham pass of radix R over X[0..H) in place (all reads, barrier, all
+// writes, barrier); HMAX bounds H, hence the groups a lane handles.  The last pass
+// (Ns = H / R, so each lane's outputs g + r Ns are contiguous across lanes) writes
+// the output row instead.
+template <int R, int HMAX, bool LAST>
+__device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, const double2* __restrict__ tw,
+                                              double2* __restrict__ out)
 {
     constexpr int GM = HMAX / (R * 256) > 0 ? HMAX / (R * 256) : 1;
     const int tid = threadIdx.x;
     const int ng = H / R;
     const int step = N / (Ns * R);
     double2 v[GM][R], b[GM][4];
-    // twiddle loads first (their latency overlaps the LDS reads and the barrier);
-    // the first pass (Ns = 1) has only unit twiddles
-    if (Ns > 1) {
+    // twiddle loads first (their latency overlaps the LDS reads and the barrier)
 #pragma unroll
-        for (int i = 0; i < GM; ++i) {
-            const int g = tid + 256 * i;
-            if (g < ng) twiddle_base<R>(tw, (g & (Ns - 1)) * step, b[i]);
-        }
+    for (int i = 0; i < GM; ++i) {
+        const int g = tid + 256 * i;
+        if (g < ng) twiddle_base<R>(tw, (g & (Ns - 1)) * step, b[i]);
     }
 #pragma unroll
     for (int i = 0; i < GM; ++i) {
@@ -227,20 +285,25 @@ __device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, 
             for (int r = 0; r < R; ++r) v[i][r] = X[pad(g + r * ng)];
         }
     }
-    __syncthreads();
+    if (!LAST) __syncthreads();
 #pragma unroll
     for (int i = 0; i < GM; ++i) {
         const int g = tid + 256 * i;
         if (g < ng) {
             const int k = g & (Ns - 1);
-            if (Ns > 1) apply_twiddles<R>(v[i], b[i]);
+            apply_twiddles<R>(v[i], b[i]);
             dft_regs<R>(v[i]);
             const int base = (g - k) * R + k;
+            if (LAST) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) X[pad(base + r * Ns)] = v[i][r];
+                for (int r = 0; r < R; ++r) out[base + r * Ns] = v[i][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) X[pad(base + r * Ns)] = v[i][r];
+            }
         }
     }
-    __syncthreads();
+    if (!LAST) __syncthreads();
 }
 
 template <int HMAX>
@@ -249,38 +312,26 @@ __global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
     extern __shared__ double2 X[];   // pad(H) + 1 entries
     const int row = blockIdx.x;      // (ring within the chunk) * nalpha + alpha
     const int N = c.ngamma, H = N / 2, L = c.lmax;
-    const int tid = threadIdx.x;
     const double2* P = reinterpret_cast<const double2*>(c.P) + (size_t)row * (L + 1);
     const double2* tw = reinterpret_cast<const double2*>(c.tw);
-    // half spectrum X_b = Z_b + Z_{b-N}, Z_0 = Re P_0, Z_k = P_k, Z_{-k} = conj(P_k)
-    for (int b = tid; b <= H; b += 256) {
-        double2 z = make_double2(0.0, 0.0);
-        if (b == 0) z = make_double2(P[0].x, 0.0);
-        else if (b <= L) z = P[b];
-        if (b > 0 && N - b <= L) z = cadd(z, cconj(P[N - b]));
-        X[pad(b)] = z;
-    }
-    __syncthreads();
-    // pack: F_k = (X_k + conj X_{H-k}) + i W^k (X_k - conj X_{H-k}), k in [0, H)
-    for (int k = tid; 2 * k <= H; k += 256) {
-        const double2 a = X[pad(k)], b = X[pad(H - k)];
-        const double2 s1 = cadd(a, cconj(b)), d1 = cmul(tw[k], csub(a, cconj(b)));
-        const double2 f1 = make_double2(s1.x - d1.y, s1.y + d1.x);
-        if (k > 0 && 2 * k < H) {
-            const double2 s2 = cadd(b, cconj(a)), d2 = cmul(tw[H - k], csub(b, cconj(a)));
-            X[pad(H - k)] = make_double2(s2.x - d2.y, s2.y + d2.x);
-        }
-        X[pad(k)] = f1;
-    }
-    __syncthreads();
-    int Ns = 1, rem = H;
-    while (rem >= 16) { stockham_pass<16, HMAX>(X, H, Ns, N, tw); Ns *= 16; rem /= 16; }
-    if (rem == 8) stockham_pass<8, HMAX>(X, H, Ns, N, tw);
-    else if (rem == 4) stockham_pass<4, HMAX>(X, H, Ns, N, tw);
-    else if (rem == 2) stockham_pass<2, HMAX>(X, H, Ns, N, tw);
-    // f_n = c[2n] + i c[2n+1]
+    // f_n = c[2n] + i c[2n+1] is the length-H transform of F
     double2* out = reinterpret_cast<double2*>(c.cube) + ((size_t)c.ring0 * c.nalpha + row) * (size_t)H;
-    for (int n = tid; n < H; n += 256) out[n] = X[pad(n)];
+    switch (H) {
+    case 1:
+        if (threadIdx.x == 0) out[0] = packed(half_spec(P, 0, N, L), half_spec(P, 1, N, L), tw[0]);
+        return;
+    case 2: first_pass<2, HMAX>(P, tw, H, N, L, X, out, true); return;
+    case 4: first_pass<4, HMAX>(P, tw, H, N, L, X, out, true); return;
+    case 8: first_pass<8, HMAX>(P, tw, H, N, L, X, out, true); return;
+    default: break;
+    }
+    first_pass<16, HMAX>(P, tw, H, N, L, X, out, H == 16);
+    int Ns = 16, rem = H / 16;
+    while (rem > 16) { stockham_pass<16, HMAX, false>(X, H, Ns, N, tw, out); Ns *= 16; rem /= 16; }
+    if (rem == 16) stockham_pass<16, HMAX, true>(X, H, Ns, N, tw, out);
+    else if (rem == 8) stockham_pass<8, HMAX, true>(X, H, Ns, N, tw, out);
+    else if (rem == 4) stockham_pass<4, HMAX, true>(X, H, Ns, N, tw, out);
+    else if (rem == 2) stockham_pass<2, HMAX, true>(X, H, Ns, N, tw, out);
 }
 
 }  // namespace
