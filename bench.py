@@ -36,14 +36,14 @@ FLOPS_PER_TERM_UNPAIRED = 9.0
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "962eb5dfc2db86d47e008330e845b35ef6f71af66e80ab693defefd5720a3d0d",
+    "kernel_source_sha256": "4694ddbc42c61d07dd896da38b14a6459527af380f97af58624a0cabd01edef5",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        "k_fwd": int(564943.5625 * 1024 * (2147483648 / (1048611.6875 * 1024))
+        "k_fwd": int(562595.0 * 1024 * (2147483648 / (1048614.0625 * 1024))
                      + 15208064.0 * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5953501.25 * 1024 * (2147483648 / (1048611.6875 * 1024))
-                     + 15228082.46875 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5943903.375 * 1024 * (2147483648 / (1048614.0625 * 1024))
+                     + 15227930.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
