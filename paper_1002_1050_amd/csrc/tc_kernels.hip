@@ -676,9 +676,14 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
             }
             if (acc_on) {
                 for (int h = 0; h < TS; h += TR) {
+                    // the group's coefficients are read before its first lane-sum store, so
+                    // the reads are in flight together instead of one round trip per step
+                    double4 kk[TR];
+#pragma unroll
+                    for (int t = 0; t < TR; ++t) kk[t] = sh_.cf[buf][s0 + h + t];
 #pragma unroll
                     for (int t = 0; t < TR; ++t) {
-                        const double4 k = sh_.cf[buf][s0 + h + t];
+                        const double4 k = kk[t];
                         double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
