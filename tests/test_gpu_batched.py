@@ -156,3 +156,48 @@ def test_plan_rejects_bad_detectors(B):
     bad[0].update(lmax=10, mbmax=11)
     with pytest.raises(B.TotalConvError, match="mbmax"):
         B.Plan(B.TC_OP_FWD, bad, 20, alm)
+
+
+def test_batched16_full_size_sampled(B, orc):
+    """The sixteen-detector plan at full size (lmax 512..4096 x mbmax 4..14, 2 lmax rings each,
+    one sky at lmax 4096; the benchmark's batched workload): per detector, sampled columns of
+    the plan equal the plain call's bit for bit and match the oracle over every ring."""
+    w = S.WORKLOADS["batched16"]
+    alm_h = S.sky_alm(w.lmax, w.sky_seed)
+    alm = dev(alm_h)
+    dets, blms = [], []
+    for d in w.detectors:
+        blm_h = d.blm()
+        blms.append(blm_h)
+        dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": d.xring(), "blm": dev(blm_h),
+                     "C": torch.empty((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128,
+                                      device="cuda")})
+    say(f"batched16 plan at full size, {len(dets)} detectors")
+    plan = B.Plan(B.TC_OP_FWD, dets, w.lmax, alm)
+    plan.execute()
+    torch.cuda.synchronize()
+    plan.close()
+    rng = np.random.Generator(np.random.PCG64(1616))
+    worst = 0.0
+    for i, (d, det) in enumerate(zip(w.detectors, dets)):
+        L, M, x = d.lmax, d.mbmax, det["cosbeta"]
+        # mb = 0 (the only non-zero beam row when the ellipticity is 0), a random even mb and a
+        # random odd mb (the beams vanish for odd mb: exact zeros)
+        mb = np.array([0, 2 * rng.integers(-(M // 2), M // 2 + 1),
+                       2 * rng.integers(-((M - 1) // 2), (M - 1) // 2 + 1) - 1], np.int32)
+        mb[2] = max(mb[2], -M)
+        ms = np.array([rng.integers(0, L + 1), rng.integers(0, L // 8 + 1), rng.integers(0, L + 1)], np.int32)
+        idx = torch.from_numpy(((mb + M) * (L + 1) + ms).astype(np.int64)).to("cuda")
+        got = det["C"].reshape(-1, x.size).index_select(0, idx).cpu()
+        a_t = truncate_sky(alm_h, w.lmax, L)
+        plain = B.totalconv_fwd(L, M, x, dev(a_t), det["blm"])
+        same = torch.equal(plain.reshape(-1, x.size).index_select(0, idx).cpu(), got)
+        del plain
+        det["C"] = None
+        torch.cuda.empty_cache()
+        assert same, f"detector {i}: batched != plain"
+        ref = orc.totalconv_fwd(L, M, x, a_t, blms[i], cols=(mb, ms))
+        g = column_gate(got.numpy(), ref)
+        say(f"  detector {i} (lmax {L}, mbmax {M}): columns {list(zip(mb.tolist(), ms.tolist()))} gate {g:.2e}")
+        worst = max(worst, g)
+    assert worst <= 1e-11
