@@ -27,6 +27,8 @@ namespace tc {
 namespace {
 
 constexpr int MS_TS = 8;          // steps between scale checks
+constexpr int MS_FL = 64;         // steps per flush of the row-gathered images (512-byte row segments)
+constexpr int MS_TB = 64;         // steps per staged coefficient block
 constexpr int MS_FOLD = -900;     // scaled values fold into plain doubles at 2^-900
 
 __device__ __forceinline__ bool wave_any_m(bool p) { return __ballot(p) != 0ull; }
@@ -75,9 +77,8 @@ __device__ __forceinline__ void row_seed(double lnAh, double lnAl, int p, int q,
 // (s = (-1)^(m-mp)).  Side 1: u = (-1)^(l+m) v with v = d_{m,mp}(pi - beta) is
 // d_{m,-mp}(beta) and goes to (m, -mp), (-mp, m), (-m, mp), (mp, -m), signs 1, s, s, 1.
 // Images 1 and 3 run along a row as the lanes' m run (stored at once, coalesced);
-// images 0 and 2 run along a row as mp runs, so they are gathered in LDS for MS_FL
-// steps and stored row by row.
-constexpr int MS_FL = 16;   // steps per flush of images 0 and 2 (16 doubles = 128 bytes)
+// images 0 and 2 run along a row as mp runs, so they are gathered in LDS for FL
+// steps and stored row by row (FL doubles per row segment).
 
 __device__ __forceinline__ void wave_lds_fence()
 {
@@ -100,13 +101,15 @@ __device__ __forceinline__ unsigned image_off(int side, int k, int l, int W, int
     return (unsigned)((row + l) * W + (col + l));
 }
 
-template <int R, int NT, int TB>
+template <int R, int NT, int TB, int FL>
 __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
 {
     static_assert(NT == 64, "one wave per workgroup");
-    static_assert(TB % MS_FL == 0 && MS_FL % MS_TS == 0, "flush period");
+    static_assert(TB % FL == 0 && FL % MS_TS == 0 && (NT % FL == 0 || FL % NT == 0), "flush period");
+    constexpr int LPR = FL < NT ? FL : NT;    // lanes per row segment in a flush
+    constexpr int RPS = NT / LPR;             // rows per flush store
     __shared__ double4 cf[2][TB];             // per step: {A, nB, F2, -}: d_next = (m A + nB) d - F2 d_prev
-    __shared__ double held[R][MS_FL][NT + 1]; // values u of the last MS_FL steps, per row
+    __shared__ double held[R][FL][NT + 1];    // values u of the last FL steps, per row
     const int tid = threadIdx.x;
     const int per_tile = 2 * a.nring;
     const int tile = blockIdx.x / per_tile;
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
                 const int s = s0 + t0 + t;
                 if (s > nsteps) break;
                 const int mp = l - s;
-                const int h = (t0 + t) % MS_FL;
+                const int h = (t0 + t) % FL;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int m = mrow[r];
@@ -220,23 +223,26 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
                     }
                 }
             }
-            // images 0 and 2 of the held steps, after every MS_FL steps and after the last:
-            // MS_FL lanes per row, NT / MS_FL rows per store
+            // images 0 and 2 of the held steps, after every FL steps and after the last:
+            // FL lanes per row, NT / FL rows per store
             const int done = s0 + t0 + MS_TS;
-            if ((t0 + MS_TS) % MS_FL == 0 || done > nsteps) {
-                const int sb = s0 + ((t0 + MS_TS - 1) / MS_FL) * MS_FL;
-                const int n = min(MS_FL, nsteps + 1 - sb);
+            if ((t0 + MS_TS) % FL == 0 || done > nsteps) {
+                const int sb = s0 + ((t0 + MS_TS - 1) / FL) * FL;
+                const int n = min(FL, nsteps + 1 - sb);
                 wave_lds_fence();
-                const int tq = tid % MS_FL;
-                const int mpf = l - (sb + tq);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    for (int q = tid / MS_FL; q < NT; q += NT / MS_FL) {
+                    for (int q = tid / LPR; q < NT; q += RPS) {
                         const int m = m_base + r * NT + q;
-                        if (tq < n && m <= l && m >= side && mpf >= m) {
-                            const double u = held[r][tq][q];
-                            out[image_off(side, 0, l, W, m, mpf)] = u;
-                            out[image_off(side, 2, l, W, m, mpf)] = ((m - mpf) & 1) ? -u : u;
+#pragma unroll
+                        for (int c = 0; c < FL; c += LPR) {
+                            const int tq = c + tid % LPR;
+                            const int mpf = l - (sb + tq);
+                            if (tq < n && m <= l && m >= side && mpf >= m) {
+                                const double u = held[r][tq][q];
+                                out[image_off(side, 0, l, W, m, mpf)] = u;
+                                out[image_off(side, 2, l, W, m, mpf)] = ((m - mpf) & 1) ? -u : u;
+                            }
                         }
                     }
                 }
@@ -267,9 +273,9 @@ int launch_matrix(const MatrixArgs& a, int R, void* stream)
 {
     const int blocks = a.ntile * 2 * a.nring;
     if (R == 1)
-        hipLaunchKernelGGL((k_wigner_row<1, 64, 32>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_wigner_row<1, 64, MS_TB, MS_FL>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
     else if (R == 2)
-        hipLaunchKernelGGL((k_wigner_row<2, 64, 32>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_wigner_row<2, 64, MS_TB, MS_FL>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
