@@ -36,14 +36,14 @@ FLOPS_PER_TERM_UNPAIRED = 9.0
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "4694ddbc42c61d07dd896da38b14a6459527af380f97af58624a0cabd01edef5",
+    "kernel_source_sha256": "8616b5a3c3b74d0e80dfbef0e3f53ebd84dce44e5dd55724af1a2fffac8804e8",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        "k_fwd": int(562595.0 * 1024 * (2147483648 / (1048614.0625 * 1024))
+        "k_fwd": int(562581.875 * 1024 * (2147483648 / (1048612.125 * 1024))
                      + 15208064.0 * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5943903.375 * 1024 * (2147483648 / (1048614.0625 * 1024))
-                     + 15227930.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5961150.75 * 1024 * (2147483648 / (1048612.125 * 1024))
+                     + 15228386.1875 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
