@@ -325,3 +325,75 @@ def test_autograd_central_differences(B):
                 fd = ((loss(alm, blm + d) - loss(alm, blm - d)) / (2 * h)).item()
                 g = gb[r, l].real.item() if unit == 1.0 else gb[r, l].imag.item()
                 assert abs(fd - g) <= 1e-8 * gmax
+
+
+def test_autograd_finite_differences_adjoint_workload(B):
+    """Forward + adjoint workload at full size (lmax 2048, mbmax 14, 4096 rings): loss
+    0.5 ||C - C_target||^2 with C_target from the second seeded sky and the same beam; the
+    torch.autograd gradients of sky and beam against central differences on 32 seeded sky
+    coefficients and 32 seeded beam coefficients (seed 7; beam rows with non-zero
+    coefficients), real and imaginary parts (real only for a_{l0}).  The loss is quadratic in
+    each coefficient, so the central difference is exact up to rounding for any step; the step
+    only sets the rounding.  Sky: 1e-3 x |coefficient|.  Beam: under this workload's beam
+    formula the coefficients span about 30 decades (C reaches 1e22 in the mb = +-14 columns),
+    and 1e-3 x |b| of a small coefficient moves C by less than C's own rounding, so the step
+    is the one that balances the two rounding errors of a central difference: the residual's
+    size in that mb row over the size of the coefficient's own response (a forward call with
+    the unit coefficient).  The gate is 1e-6 x max|g| (over the sky, resp. the beam, gradient)."""
+    from paper_1002_1050_amd import TotalConv
+    w = S.WORKLOADS["adjoint"]
+    L, M = w.lmax, w.mbmax
+    x = w.xring()
+    alm_h, blm_h = w.alm(), w.blm()
+    alm = dev(alm_h).requires_grad_(True)
+    blm = dev(blm_h).requires_grad_(True)
+    say(f"autograd finite differences L={L} M={M} nring={x.size}")
+    with torch.no_grad():
+        T = B.totalconv_fwd(L, M, x, dev(S.sky_alm(L, w.target_seed)), blm.detach())
+    C = TotalConv.apply(alm, blm, x, L, M)
+    loss = 0.5 * torch.sum(torch.abs(C - T) ** 2)
+    loss.backward()
+    R = (C.detach() - T)
+    del C
+    ga, gb = alm.grad.clone(), blm.grad.clone()
+    a0, b0 = alm.detach(), blm.detach()
+    Cp = torch.empty_like(T)
+    Cm = torch.empty_like(T)
+
+    def central(da, db, h):
+        # (L(p + h) - L(p - h)) / 2h with |Cp - T|^2 - |Cm - T|^2 = Re((Cp - Cm) conj(Cp + Cm - 2T))
+        B.totalconv_fwd(L, M, x, a0 + da, b0 + db, out=Cp)
+        B.totalconv_fwd(L, M, x, a0 - da, b0 - db, out=Cm)
+        return 0.5 * torch.sum(((Cp - Cm) * torch.conj(Cp + Cm - 2.0 * T)).real).item() / (2.0 * h)
+
+    rng = np.random.Generator(np.random.PCG64(7))
+    za, zb = torch.zeros_like(a0), torch.zeros_like(b0)
+    worst_a = worst_b = 0.0
+    gmax_a = ga.abs().max().item()
+    gmax_b = gb.abs().max().item()
+    with torch.no_grad():
+        for k in rng.choice(alm_h.size, 32, replace=False):
+            m = int(np.searchsorted([S.alm_index(L, mm, mm) for mm in range(L + 2)], k, side="right") - 1)
+            h = 1e-3 * abs(alm_h[k])
+            for unit in ((1.0,) if m == 0 else (1.0, 1j)):
+                d = za.clone()
+                d[k] = h * unit
+                fd = central(d, zb, h)
+                g = ga[k].real.item() if unit == 1.0 else ga[k].imag.item()
+                worst_a = max(worst_a, abs(fd - g) / gmax_a)
+        rows = [r for r in range(2 * M + 1) if np.any(blm_h[r] != 0)]
+        for _ in range(32):
+            r = int(rng.choice(rows))
+            l = int(rng.integers(abs(r - M), L + 1))
+            unit_b = zb.clone()
+            unit_b[r, l] = 1.0
+            B.totalconv_fwd(L, M, x, a0, unit_b, out=Cp)
+            h = R[r].abs().max().item() / Cp[r].abs().max().item()
+            for unit in (1.0, 1j):
+                d = zb.clone()
+                d[r, l] = h * unit
+                fd = central(za, d, h)
+                g = gb[r, l].real.item() if unit == 1.0 else gb[r, l].imag.item()
+                worst_b = max(worst_b, abs(fd - g) / gmax_b)
+    say(f"  sky: max |fd - g| / max|g| = {worst_a:.3e};  beam: {worst_b:.3e}")
+    assert worst_a <= 1e-6 and worst_b <= 1e-6
