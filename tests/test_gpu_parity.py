@@ -251,10 +251,13 @@ def test_adj_dot_product_medium(B):
     assert abs(lhs - rhs_b) <= 1e-12 * abs(lhs)
 
 
-def test_adj_large_sampled_sky_gradient(B, orc):
-    """lmax 2048 forward + adjoint with loss 0.5||C - C_target||^2; the oracle evaluates the sky
-    gradient for sampled msky (every mb and ring of those columns)."""
-    w = S.WORKLOADS["adjoint"]
+@pytest.mark.parametrize("name,msel", [("adjoint", [0, 7, 1500, 2048]), ("lmax4096", [0, 9, 3000, 4096])])
+def test_adj_large_sampled_sky_gradient(B, orc, name, msel):
+    """Forward + adjoint at full size (lmax 2048 / 4096, the latter being the benchmark's
+    launch) with loss 0.5||C - C_target||^2; the oracle evaluates the sky gradient for sampled
+    msky (every mb and ring of those columns); the dot-product identities <G, C> = <sky_bar, a>
+    = <b, beam_bar> check the whole of both gradients."""
+    w = S.WORKLOADS[name]
     x, alm, blm = w.xring(), w.alm(), w.blm()
     target = S.sky_alm(w.lmax, w.target_seed)
     say(f"adjoint workload L={w.lmax} M={w.mbmax} nring={w.nring}")
@@ -262,10 +265,15 @@ def test_adj_large_sampled_sky_gradient(B, orc):
     C = B.totalconv_fwd(w.lmax, w.mbmax, x, a_d, b_d)
     T = B.totalconv_fwd(w.lmax, w.mbmax, x, dev(target), b_d)
     G = C - T
+    lhs = torch.vdot(G.flatten(), C.flatten()).item()
     del C, T
     ga, gb = B.totalconv_adj(w.lmax, w.mbmax, x, a_d, b_d, G)
+    rhs_a = torch.vdot(ga.flatten(), a_d.flatten()).item()
+    rhs_b = torch.sum(torch.conj(b_d) * gb).item()
+    say(f"  <G,C>={lhs:.9e}  <ga,a>={rhs_a:.9e}  <b,gb>={rhs_b:.9e}")
+    assert abs(lhs - rhs_a) <= GATE_C * abs(lhs)
+    assert abs(lhs - rhs_b) <= GATE_C * abs(lhs)
     ga = ga.cpu().numpy()
-    msel = [0, 7, 1500, 2048]
     nb = 2 * w.mbmax + 1
     cols_mb = np.repeat(np.arange(-w.mbmax, w.mbmax + 1), len(msel)).astype(np.int32)
     cols_ms = np.tile(np.array(msel), nb).astype(np.int32)
