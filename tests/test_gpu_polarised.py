@@ -179,3 +179,34 @@ def test_polarised_autograd_central_differences(B, summed):
                     fd = ((loss(alms, plus) - loss(alms, minus)) / (2 * h)).item()
                     g = grads[3 + p][r, l]
                     assert abs(fd - (g.real.item() if unit == 1.0 else g.imag.item())) <= 1e-8 * gmax
+
+
+def test_polarised_full_size_sampled(B, orc):
+    """The benchmark's polarised launch at full size: lmax 4096, mbmax 14, 8192 rings, three
+    pairs (the workload's sky and beam plus two seeded skies and random beams), built-in tile;
+    sampled columns of every separate output and of the summed output against the oracle over
+    every ring."""
+    w = S.WORKLOADS["lmax4096"]
+    L, M, x = w.lmax, w.mbmax, w.xring()
+    alms = [w.alm()] + [S.sky_alm(L, w.sky_seed + 1 + p) for p in range(2)]
+    blms = [w.blm()] + [S.random_beam(L, M, 77 + p) for p in range(2)]
+    da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+    rng = np.random.Generator(np.random.PCG64(4096))
+    mb = np.concatenate([[0, M, -M, 1], rng.integers(-M, M + 1, 8)]).astype(np.int32)
+    ms = np.concatenate([[0, L, 1, L // 2], (rng.random(8) ** 0.7 * (L + 1)).astype(int)]).astype(np.int32)
+    ms = np.minimum(ms, L)
+    idx = torch.from_numpy(((mb + M) * (L + 1) + ms).astype(np.int64)).to("cuda")
+    say(f"fwd_pol full size L={L} M={M} nring={x.size}, three pairs")
+    sep = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SEPARATE)
+    got = [c.reshape(-1, x.size).index_select(0, idx).cpu().numpy() for c in sep]
+    del sep
+    torch.cuda.empty_cache()
+    tot = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0]
+    got_t = tot.reshape(-1, x.size).index_select(0, idx).cpu().numpy()
+    del tot
+    torch.cuda.empty_cache()
+    ref = [orc.totalconv_fwd(L, M, x, alms[p], blms[p], cols=(mb, ms)) for p in range(3)]
+    gs = max(column_gate(got[p], ref[p]) for p in range(3))
+    gt = column_gate(got_t, ref[0] + ref[1] + ref[2])
+    say(f"  {mb.size} columns: separate {gs:.2e}, summed {gt:.2e}")
+    assert gs <= GATE and gt <= GATE
