@@ -113,3 +113,40 @@ def test_cube_ring_chunks_give_the_same_cube(B):
         B.timing_enable(0)
         B.set_tile(B.TC_OP_CUBE, 0)
     assert torch.equal(whole, chunked)
+
+
+def test_cube_full_size_from_the_forward_sampled(B, orc):
+    """The benchmark's cube launch at full size: the forward's C at lmax 4096, mbmax 14 on all
+    8192 rings (eight ring chunks), nalpha 29, ngamma 8192.  Sampled points, on rings on both
+    sides of the chunk boundaries, against the oracle's double sum over the same C rows; gate
+    per ring relative to that ring's max |c|."""
+    w = S.WORKLOADS["lmax4096"]
+    L, M, x = w.lmax, w.mbmax, w.xring()
+    Na, Ng = 2 * M + 1, 2 * L
+    C = B.totalconv_fwd(L, M, x, torch.from_numpy(w.alm()).cuda(), torch.from_numpy(w.blm()).cuda())
+    say(f"datacube full size L={L} M={M} nring={x.size} nalpha={Na} ngamma={Ng}")
+    B.timing_enable(64)
+    cube = B.totalconv_datacube(L, M, C, Na, Ng)
+    torch.cuda.synchronize()
+    nchunk = len(B.timing_read(B.TC_OP_CUBE, 64))
+    B.timing_enable(0)
+    chunk = (1 << 31) // (16 * Na * (L + 1))      # rings per chunk: alpha sums of a chunk within 2 GiB
+    assert nchunk == -(-x.size // chunk)
+    rings = np.unique(np.clip(np.array([0, chunk - 1, chunk, 3 * chunk + 5, x.size // 2, x.size - 1]), 0, x.size - 1))
+    say(f"  {nchunk} ring chunks; sampled rings {rings.tolist()}")
+    sel = torch.from_numpy(rings).cuda()
+    Cs = C.index_select(2, sel).cpu().numpy()
+    rows = cube.index_select(0, sel)
+    scale = rows.abs().reshape(rings.size, -1).max(dim=1).values.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(8192))
+    k = np.repeat(np.arange(rings.size), 40)
+    a = rng.integers(0, Na, k.size)
+    g = rng.integers(0, Ng, k.size)
+    g[:4] = [0, Ng // 2, 1, Ng - 1]
+    got = rows.cpu().numpy()[k, a, g]
+    del C, cube, rows
+    torch.cuda.empty_cache()
+    ref = orc.datacube(L, M, Cs, Na, Ng, points=(k, a, g))
+    err = float((np.abs(got - ref) / scale[k]).max())
+    say(f"  {k.size} points: max |dc| / max|c| of the ring {err:.2e}")
+    assert nchunk > 1 and err <= 1e-12
