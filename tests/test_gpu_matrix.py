@@ -81,3 +81,20 @@ def test_matrix_tiles_agree(B):
     b = B.wigner_d_matrix(l, x)
     B.set_tile(B.TC_OP_MATRIX, 0)
     assert torch.equal(a, b)
+
+
+def test_matrix_benchmark_launch_sampled(B, orc):
+    """The benchmark's launch: the full matrix at l = 4096 on its 16 rings (every ring, both
+    sides, all row tiles), sampled elements of every ring against the oracle."""
+    l, nring = 4096, 16
+    x = S.ring_cosines(2 * nring + 1)[1:nring + 1]
+    say(f"wigner_d_matrix l={l} nring={nring} (benchmark rings)")
+    got = B.wigner_d_matrix(l, x)
+    rng = np.random.Generator(np.random.PCG64(16 * l))
+    m = np.concatenate([rng.integers(-l, l + 1, 300), [l, -l, 0, l, -l], np.arange(l - 70, l + 1)])
+    mp = np.concatenate([rng.integers(-l, l + 1, 300), [l, -l, 0, -l, l], rng.integers(-l, l + 1, 71)])
+    ref = orc.wigner_d(l, m, mp, x)[:, l, :]
+    g = got.cpu().numpy()[:, m + l, mp + l].T
+    err = np.abs(g - ref).max()
+    say(f"  {m.size} elements x {nring} rings: max abs err {err:.2e}")
+    assert err <= 1e-10
