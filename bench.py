@@ -29,6 +29,27 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 128 FP64 flop/clk x 2.4 GHz
 # terms, and each term adds a complex weight times a real d (4 flops).
 FLOPS_PER_TERM_PAIRED = 6.5
 FLOPS_PER_TERM_UNPAIRED = 9.0
+# forward on a column whose beam rows mb and -mb differ by a sign: one complex weight per
+# step serves both rings of a mirror pair (5 recursion + 4 accumulation flops per 2 terms)
+FLOPS_PER_TERM_PAIRED_ROWS = 4.5
+
+
+def forward_flops_per_term(w, blm, paired):
+    """Algorithmic flops per term of the forward: 4.5 on the columns whose beam rows mb and -mb
+    are equal up to a sign for every l >= |mb| (the library then sums even and odd l apart),
+    6.5 on the others (9 without mirror pairs), weighted by the terms of each column."""
+    if not paired:
+        return FLOPS_PER_TERM_UNPAIRED
+    L, M = w.lmax, w.mbmax
+    ms = np.arange(L + 1)
+    tot = fast = 0
+    for mb in range(-M, M + 1):
+        n = float(np.sum(L - np.maximum(abs(mb), ms) + 1))
+        p, m = blm[mb + M, abs(mb):], blm[-mb + M, abs(mb):]
+        tot += n
+        if np.array_equal(m, p) or np.array_equal(m, -p):
+            fast += n
+    return (fast * FLOPS_PER_TERM_PAIRED_ROWS + (tot - fast) * FLOPS_PER_TERM_PAIRED) / tot
 
 
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over
@@ -401,8 +422,11 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = passes * terms / (elapsed / args.steps)
     paired = bool(np.all(x[::-1][: w.nring // 2] == -x[: w.nring // 2]))
-    fpt = FLOPS_PER_TERM_PAIRED if paired else FLOPS_PER_TERM_UNPAIRED
+    fpt_adj = FLOPS_PER_TERM_PAIRED if paired else FLOPS_PER_TERM_UNPAIRED
+    fpt_fwd = forward_flops_per_term(w, blm_h, paired)
     dom_name, dom_ms = ("k_adj", kadj_ms) if kadj_ms > kfwd_ms else ("k_fwd", kfwd_ms)
+    fpt = fpt_adj if dom_name == "k_adj" else fpt_fwd
+    fpt_other = fpt_fwd if dom_name == "k_adj" else fpt_adj
     achieved = fpt * terms / (dom_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu",
@@ -418,7 +442,8 @@ def main():
         "launch_ms_per_step": [round(v, 3) for v in (k_adj if dom_name == "k_adj" else k_fwd)],
         "other_kernel": {"name": "k_fwd" if dom_name == "k_adj" else "k_adj",
                          "launch_ms": round(kfwd_ms if dom_name == "k_adj" else kadj_ms, 3),
-                         "frac": round(fpt * terms / ((kfwd_ms if dom_name == "k_adj" else kadj_ms) or float("inf"))
+                         "flops_per_term": round(fpt_other, 4),
+                         "frac": round(fpt_other * terms / ((kfwd_ms if dom_name == "k_adj" else kadj_ms) or float("inf"))
                                        / 1e9 / FP64_VECTOR_PEAK_TFLOPS, 4)},
     }
     result = {

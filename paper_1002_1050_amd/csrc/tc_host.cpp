@@ -120,7 +120,7 @@ int timed_launch(int op, void* stream, F launch)
 
 struct Layout {
     size_t ring = 0, slots = 0, colmb = 0, colms = 0, lna = 0, tables_end = 0;
-    size_t U = 0, V = 0, total = 0;
+    size_t U = 0, V = 0, sym = 0, total = 0;
     int nslot = 0, ncol = 0, ntile = 0;
     long long P = 0;
 };
@@ -152,6 +152,9 @@ Layout make_layout(int op, int lmax, int mbmax_or_npair, int nring, const double
     L.colms = off; off = align_up(off + sizeof(int) * (size_t)L.ncol);
     L.lna = off;   off = align_up(off + sizeof(double) * 2 * (size_t)L.ncol);
     L.tables_end = off;
+    if (op == TC_OP_FWD || op == TC_OP_FWD_POL) {   // beam row signs, computed on the device
+        L.sym = off; off = align_up(off + sizeof(int) * (size_t)(2 * mbmax_or_npair + 1));
+    }
     if (op == TC_OP_ADJ) {
         L.P = (long long)(lmax + 1) * (lmax + 2) / 2;
         const size_t ubytes = (size_t)16 * (size_t)L.ntile * (size_t)(2 * mbmax_or_npair + 1) * (size_t)L.P;
@@ -326,6 +329,12 @@ int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int 
     a.sum = sum;
     for (int p = 0; p < npair; ++p) { a.alm[p] = alm[p]; a.blm[p] = blm[p]; }
     for (int c = 0; c < nout; ++c) a.C[c] = C[c];
+    a.beam_sym = nullptr;
+    if (npair == 1) {   // scalar convolution: beam rows related by a sign take the even / odd sums
+        int* sym = reinterpret_cast<int*>(static_cast<char*>(workspace) + L.sym);
+        if ((rc = tc::launch_beam_symmetry(blm[0], lmax, mbmax, sym, stream))) return hip_fail(rc, "beam symmetry launch");
+        a.beam_sym = sym;
+    }
     rc = timed_launch(op, stream, [&] { return tc::launch_fwd(a, t, stream); });
     return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
 }
@@ -899,6 +908,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
             a.col = col_ptrs(ws, L);
             a.npair = 1; a.sum = 0; a.alm[0] = alm; a.blm[0] = d.blm; a.C[0] = d.C;
+            a.beam_sym = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.sym);
         } else {
             tc::AdjArgs& a = aa[i];
             a = tc::AdjArgs{};
@@ -947,6 +957,9 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     int* counter = reinterpret_cast<int*>(dm + counter_off);
     const int* d_items = reinterpret_cast<const int*>(dm + items_off);
     if (!rc) rc = tc::launch_reset_counter(counter, cs);
+    for (int i = 0; i < ndet && !rc && op == TC_OP_FWD; ++i)   // beam row signs, on every execution
+        rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax,
+                                      reinterpret_cast<int*>(dm + base[i] + lay[i].sym), cs);
     if (!rc && op == TC_OP_FWD)
         rc = tc::launch_fwd_queue(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, counter,
                                   p->tile, p->grid, cs);

@@ -52,6 +52,8 @@ struct FwdArgs {
     const double* alm[3];  // packed sky of each pair (complex)
     const double* blm[3];  // [2M+1][L+1] complex, per pair
     double* C[3];          // [2M+1][L+1][nring] complex, per output
+    const int* beam_sym;   // scalar convolution: per beam row mb + M, s = +-1 if b_{l,-mb} = s b_{l,mb}
+                           // for every l >= |mb|, else 0 (from k_beam_symmetry); null: not used
 };
 
 struct AdjArgs {
@@ -108,6 +110,7 @@ int cube_set_lds_limits();
 // Kernel launchers (tc_kernels.hip).  Return a hipError_t value (0 on success).
 int launch_wigner(const WignerArgs& a, Tile t, void* stream);
 int launch_fwd(const FwdArgs& a, Tile t, void* stream);
+int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void* stream);
 int launch_adj(const AdjArgs& a, Tile t, void* stream);
 int launch_adj_epilogue(const EpiArgs& e, void* stream);
 

@@ -406,12 +406,53 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[1 + NC], int s0,
     }
 }
 
+// Beam rows mb and -mb related by a sign s (b_{l,-mb} = s b_{l,mb}, as for a beam with
+// real coefficients): then w2 = s (-1)^(l-msky) w1, and the direct and mirror sums both
+// follow from the sums of w1 d over the even and over the odd steps of the walk, so a
+// step adds w1 d into one of two sums (2 instead of 4 fused multiply-adds per chain).
+// The step parity is that of t (blocks and groups have even lengths): P0 += at even t,
+// P1 at odd t, in the c1 and c2 registers of the general form.
+template <int R, bool ACC>
+__device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[2], int s0,
+                                               const double (&x)[R], double (&d)[R], double (&dp)[R],
+                                               double (&p0r)[R], double (&p0i)[R],
+                                               double (&p1r)[R], double (&p1i)[R])
+{
+#pragma unroll
+    for (int t = 0; t < TS; ++t) {
+        const double4 k = cf[s0 + t][0];
+        double2 w = make_double2(0.0, 0.0);
+        if (ACC) {
+            const double4 v = cf[s0 + t][1];
+            w = make_double2(v.x, v.y);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ACC) {
+                if ((t & 1) == 0) {
+                    p0r[r] = fma(w.x, d[r], p0r[r]);
+                    p0i[r] = fma(w.y, d[r], p0i[r]);
+                } else {
+                    p1r[r] = fma(w.x, d[r], p1r[r]);
+                    p1i[r] = fma(w.y, d[r], p1i[r]);
+                }
+            }
+            const double u = fma(x[r], k.x, k.y);
+            const double dn = fma(-k.z, dp[r], u * d[r]);
+            dp[r] = d[r];
+            d[r] = dn;
+        }
+    }
+}
+
 // One (column, ring tile) work item of the forward.  cf per l of the current and the
 // next block: {A, nB, F2, -}, then {w1r, w1i, w2r, w2i} of each output.
-template <int R, int NT, int TB, int NC, int NP>
-__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][1 + NC])
+template <int R, int NT, int TB, int NC, int NP, bool ROWS>
+__device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int tile, int rows_sign,
+                                                double4 (&cf)[2][TB][1 + NC])
 {
     static_assert(NC == 1 || NC == NP, "one output per pair, or one summed output");
+    static_assert(!ROWS || (NC == 1 && NP == 1), "the even / odd sums serve the scalar convolution");
     const int tid = threadIdx.x;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
@@ -484,10 +525,12 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
             } else if (!acc_on) {
                 acc_on = wave_any(lane_may_be_hot<R>(d, dp, thr));
             }
-            if (acc_on)
-                fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
-            else
+            if (!acc_on)
                 fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+            else if constexpr (ROWS)
+                fwd_steps_rows<R, true>(cf[buf], s0, x, d, dp, c1r[0], c1i[0], c2r[0], c2i[0]);
+            else
+                fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
         }
         if (stage) stage_block<NC, NP>(a, raw, lb + TB + st, mb, ms, cf[buf ^ 1][st]);
         __syncthreads();
@@ -495,6 +538,16 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
 
     const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+    if constexpr (ROWS) {
+        // direct sum P0 + P1; mirror sum s (-1)^(msky + l0) (P0 - P1)
+        const double sg = ((ms + l0) & 1) ? -(double)rows_sign : (double)rows_sign;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double er = c1r[0][r] + c2r[0][r], ei = c1i[0][r] + c2i[0][r];
+            const double mr = sg * (c1r[0][r] - c2r[0][r]), mi = sg * (c1i[0][r] - c2i[0][r]);
+            c1r[0][r] = er; c1i[0][r] = ei; c2r[0][r] = mr; c2i[0][r] = mi;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double2* C = reinterpret_cast<double2*>(a.C[c]);
@@ -507,6 +560,21 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
             }
         }
     }
+}
+
+// A work item takes the even / odd form when the column's beam rows are related by a sign
+// (a wave-uniform choice made once per item).
+template <int R, int NT, int TB, int NC, int NP>
+__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][1 + NC])
+{
+    if constexpr (NC == 1 && NP == 1) {
+        const int s = a.beam_sym ? a.beam_sym[a.col.mb[ci] + a.mbmax] : 0;
+        if (s != 0) {
+            fwd_column_walk<R, NT, TB, 1, 1, true>(a, ci, tile, s, cf);
+            return;
+        }
+    }
+    fwd_column_walk<R, NT, TB, NC, NP, false>(a, ci, tile, 0, cf);
 }
 
 template <int R, int NT, int TB, int NC, int NP>
@@ -903,6 +971,36 @@ int launch_wigner(const WignerArgs& a, Tile t, void* stream)
     X(2, 64, 1, 3) X(4, 64, 1, 3) X(2, 32, 2, 2) X(4, 32, 2, 2) X(2, 64, 2, 2) X(4, 64, 2, 2)  \
     X(2, 32, 3, 3) X(4, 32, 3, 3) X(2, 64, 3, 3) X(4, 64, 3, 3)
 #define TC_ADJ_VARIANTS(X) X(2, 32, 4) X(4, 32, 4) X(8, 32, 4) X(2, 64, 4) X(4, 64, 4) X(8, 64, 4)
+
+// Beam rows related by a sign: sym[M + mb] = sym[M - mb] = s if b_{l,-mb} = s b_{l,mb} for
+// every l >= |mb| (s = +1 when both signs hold, as for zero rows and mb = 0), else 0.
+__global__ void __launch_bounds__(256) k_beam_symmetry(const double2* __restrict__ blm, int lmax, int mbmax,
+                                                       int* __restrict__ sym)
+{
+    const int mb = blockIdx.x;   // 0 .. mbmax
+    const double2* bp = blm + (size_t)(mbmax + mb) * (lmax + 1);
+    const double2* bm = blm + (size_t)(mbmax - mb) * (lmax + 1);
+    bool plus = true, minus = true;
+    for (int l = mb + (int)threadIdx.x; l <= lmax; l += 256) {
+        const double2 p = bp[l], m = bm[l];
+        plus = plus && (m.x == p.x) && (m.y == p.y);
+        minus = minus && (m.x == -p.x) && (m.y == -p.y);
+    }
+    plus = __syncthreads_and(plus);
+    minus = __syncthreads_and(minus);
+    if (threadIdx.x == 0) {
+        const int s = plus ? 1 : (minus ? -1 : 0);
+        sym[mbmax + mb] = s;
+        sym[mbmax - mb] = s;
+    }
+}
+
+int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void* stream)
+{
+    hipLaunchKernelGGL(k_beam_symmetry, dim3(mbmax + 1), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const double2*>(blm), lmax, mbmax, sym);
+    return (int)hipGetLastError();
+}
 
 int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 {
