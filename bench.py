@@ -57,14 +57,14 @@ def forward_flops_per_term(w, blm, paired):
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "8616b5a3c3b74d0e80dfbef0e3f53ebd84dce44e5dd55724af1a2fffac8804e8",
+    "kernel_source_sha256": "e0d1d4a6e66006ae481fa534fffb5cd7bb577fde1ec1b6c7cd441ab8bafd9ca1",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        "k_fwd": int(562581.875 * 1024 * (2147483648 / (1048612.125 * 1024))
+        "k_fwd": int(562748.8125 * 1024 * (2147483648 / (1048609.875 * 1024))
                      + 15208064.0 * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5961150.75 * 1024 * (2147483648 / (1048612.125 * 1024))
-                     + 15228386.1875 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5964502.875 * 1024 * (2147483648 / (1048609.875 * 1024))
+                     + 15228253.96875 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
