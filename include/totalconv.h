@@ -51,7 +51,7 @@ extern "C" {
 #define TC_EINVAL (-1)        /* invalid argument                         */
 #define TC_EHIP (-2)          /* a HIP runtime call failed                */
 #define TC_ENOMEM (-3)        /* workspace too small or allocation failed */
-#define TC_EUNSUPPORTED (-4)  /* valid request this build cannot serve    */
+#define TC_EUNSUPPORTED (-4)  /* valid request the library cannot serve   */
 
 #define TC_OP_WIGNER 0
 #define TC_OP_FWD 1
