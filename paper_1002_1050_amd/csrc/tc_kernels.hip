@@ -46,6 +46,12 @@ constexpr int min_waves() { return R >= 8 ? 2 : (R >= 4 ? 3 : 4); }
 template <int R, int NC, int NP>
 constexpr int fwd_min_waves() { return NC == 1 ? min_waves<R>() : (R >= 4 ? 2 : 3); }
 
+// The forward's even / odd form holds 2 complex sums per chain in the same registers but
+// needs fewer temporaries: R = 4 fits 4 waves per SIMD (its few spills sit outside the
+// step loop), which hides more of each step's broadcast LDS reads.
+template <int R>
+constexpr int rows_min_waves() { return R >= 8 ? 2 : 4; }
+
 // The adjoint's LDS (about 53 KB per workgroup with TB = 32, 62 KB with TB = 64)
 // caps residency at 3 or 2 workgroups (waves per SIMD) per CU.
 template <int R, int TB>
@@ -577,12 +583,28 @@ __device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, d
     fwd_column_walk<R, NT, TB, NC, NP, false>(a, ci, tile, 0, cf);
 }
 
+// The scalar forward runs as two launches over every (column, tile): k_fwd_rows takes the
+// columns whose beam rows are equal up to a sign, k_fwd the others (and every polarised
+// column); a workgroup whose column belongs to the other launch returns at once.
 template <int R, int NT, int TB, int NC, int NP>
 __global__ void __launch_bounds__(NT, (fwd_min_waves<R, NC, NP>())) k_fwd(const FwdArgs a)
 {
     __shared__ double4 cf[2][TB][1 + NC];
     const int ci = blockIdx.x / a.ntile;
-    fwd_column<R, NT, TB, NC, NP>(a, ci, blockIdx.x - ci * a.ntile, cf);
+    if constexpr (NC == 1 && NP == 1) {
+        if (a.beam_sym && a.beam_sym[a.col.mb[ci] + a.mbmax] != 0) return;
+    }
+    fwd_column_walk<R, NT, TB, NC, NP, false>(a, ci, blockIdx.x - ci * a.ntile, 0, cf);
+}
+
+template <int R, int NT, int TB>
+__global__ void __launch_bounds__(NT, (rows_min_waves<R>())) k_fwd_rows(const FwdArgs a)
+{
+    __shared__ double4 cf[2][TB][2];
+    const int ci = blockIdx.x / a.ntile;
+    const int s = a.beam_sym[a.col.mb[ci] + a.mbmax];
+    if (s == 0) return;
+    fwd_column_walk<R, NT, TB, 1, 1, true>(a, ci, blockIdx.x - ci * a.ntile, s, cf);
 }
 
 // Persistent form: each workgroup takes (detector, column, tile) items from a
@@ -937,6 +959,29 @@ int launch_grid(void (*kern)(Args), const Args& a, int blocks, int nt, void* str
     return (int)hipGetLastError();
 }
 
+// Beam rows related by a sign: sym[M + mb] = sym[M - mb] = s if b_{l,-mb} = s b_{l,mb} for
+// every l >= |mb| (s = +1 when both signs hold, as for zero rows and mb = 0), else 0.
+__global__ void __launch_bounds__(256) k_beam_symmetry(const double2* __restrict__ blm, int lmax, int mbmax,
+                                                       int* __restrict__ sym)
+{
+    const int mb = blockIdx.x;   // 0 .. mbmax
+    const double2* bp = blm + (size_t)(mbmax + mb) * (lmax + 1);
+    const double2* bm = blm + (size_t)(mbmax - mb) * (lmax + 1);
+    bool plus = true, minus = true;
+    for (int l = mb + (int)threadIdx.x; l <= lmax; l += 256) {
+        const double2 p = bp[l], m = bm[l];
+        plus = plus && (m.x == p.x) && (m.y == p.y);
+        minus = minus && (m.x == -p.x) && (m.y == -p.y);
+    }
+    plus = __syncthreads_and(plus);
+    minus = __syncthreads_and(minus);
+    if (threadIdx.x == 0) {
+        const int s = plus ? 1 : (minus ? -1 : 0);
+        sym[mbmax + mb] = s;
+        sym[mbmax - mb] = s;
+    }
+}
+
 }  // namespace
 
 // Built tile variants.  Forward and adjoint: R in {2, 4, 8}, TB in {32, 64};
@@ -972,29 +1017,6 @@ int launch_wigner(const WignerArgs& a, Tile t, void* stream)
     X(2, 32, 3, 3) X(4, 32, 3, 3) X(2, 64, 3, 3) X(4, 64, 3, 3)
 #define TC_ADJ_VARIANTS(X) X(2, 32, 4) X(4, 32, 4) X(8, 32, 4) X(2, 64, 4) X(4, 64, 4) X(8, 64, 4)
 
-// Beam rows related by a sign: sym[M + mb] = sym[M - mb] = s if b_{l,-mb} = s b_{l,mb} for
-// every l >= |mb| (s = +1 when both signs hold, as for zero rows and mb = 0), else 0.
-__global__ void __launch_bounds__(256) k_beam_symmetry(const double2* __restrict__ blm, int lmax, int mbmax,
-                                                       int* __restrict__ sym)
-{
-    const int mb = blockIdx.x;   // 0 .. mbmax
-    const double2* bp = blm + (size_t)(mbmax + mb) * (lmax + 1);
-    const double2* bm = blm + (size_t)(mbmax - mb) * (lmax + 1);
-    bool plus = true, minus = true;
-    for (int l = mb + (int)threadIdx.x; l <= lmax; l += 256) {
-        const double2 p = bp[l], m = bm[l];
-        plus = plus && (m.x == p.x) && (m.y == p.y);
-        minus = minus && (m.x == -p.x) && (m.y == -p.y);
-    }
-    plus = __syncthreads_and(plus);
-    minus = __syncthreads_and(minus);
-    if (threadIdx.x == 0) {
-        const int s = plus ? 1 : (minus ? -1 : 0);
-        sym[mbmax + mb] = s;
-        sym[mbmax - mb] = s;
-    }
-}
-
 int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void* stream)
 {
     hipLaunchKernelGGL(k_beam_symmetry, dim3(mbmax + 1), dim3(256), 0, (hipStream_t)stream,
@@ -1006,7 +1028,14 @@ int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 {
     const int blocks = a.ncol * a.ntile;
     if (a.npair == 1) {
-#define X(r, tb) if (t.R == r && t.TB == tb) return launch_grid(k_fwd<r, 256, tb, 1, 1>, a, blocks, 256, stream);
+#define X(r, tb)                                                                              \
+    if (t.R == r && t.TB == tb) {                                                             \
+        if (a.beam_sym) {                                                                     \
+            const int rc = launch_grid(k_fwd_rows<r, 256, tb>, a, blocks, 256, stream);       \
+            if (rc) return rc;                                                                \
+        }                                                                                     \
+        return launch_grid(k_fwd<r, 256, tb, 1, 1>, a, blocks, 256, stream);                  \
+    }
         TC_FWD_VARIANTS(X)
 #undef X
         return (int)hipErrorInvalidValue;
