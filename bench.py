@@ -57,14 +57,15 @@ def forward_flops_per_term(w, blm, paired):
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "e0d1d4a6e66006ae481fa534fffb5cd7bb577fde1ec1b6c7cd441ab8bafd9ca1",
+    "kernel_source_sha256": "4164e23a646c74c722436435a281a9f65611440be0475ce417b0e5129eaa67aa",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        "k_fwd": int(562748.8125 * 1024 * (2147483648 / (1048609.875 * 1024))
-                     + 15208064.0 * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5964502.875 * 1024 * (2147483648 / (1048609.875 * 1024))
-                     + 15228253.96875 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        # (the forward: its two launches, k_fwd_rows and k_fwd, together)
+        "k_fwd": int((2907582.75 + 3722.625) * 1024 * (2147483648 / (1048610.375 * 1024))
+                     + (21857442.25 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5962050.9375 * 1024 * (2147483648 / (1048610.375 * 1024))
+                     + 15228209.59375 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
