@@ -35,6 +35,15 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// Streaming store of a cube element (written once, read by no later pass here).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(double2* p, double2 v)
+{
+    nt_d2 w;
+    w.x = v.x; w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
+}
+
 // ------------------------------------------------------------ alpha sums
 constexpr int CA_T = 16;    // rings and msky values per workgroup tile (16 x 16 = 256 lanes)
 constexpr int CA_Q = 8;     // alpha values per transposed store
@@ -248,7 +257,7 @@ __device__ __forceinline__ void first_pass(const double2* __restrict__ P, const 
             dft_regs<R>(v[i]);
             if (last) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) out[g * R + r] = v[i][r];
+                for (int r = 0; r < R; ++r) store_stream(out + g * R + r, v[i][r]);
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) X[pad(g * R + r)] = v[i][r];
@@ -296,7 +305,7 @@ __device__ __forceinline__ void stockham_pass(double2* X, int H, int Ns, int N, 
             const int base = (g - k) * R + k;
             if (LAST) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) out[base + r * Ns] = v[i][r];
+                for (int r = 0; r < R; ++r) store_stream(out + base + r * Ns, v[i][r]);
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) X[pad(base + r * Ns)] = v[i][r];
