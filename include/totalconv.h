@@ -272,7 +272,10 @@ typedef struct tc_detector {
  * be NULL) receives the sky gradient summed over all detectors.  The plan keeps
  * the device pointers it is given (they must stay valid while it is used) and
  * owns its tables and partial-sum buffers (device memory allocated here and
- * released by tc_plan_destroy).  Creation is synchronous on `stream`.
+ * released by tc_plan_destroy).  Creation is synchronous on `stream`.  The
+ * pointed-to data may change between executions: each execution reads the
+ * beams, sky and cotangents afresh (including, for the forward, which beam rows
+ * are equal up to a sign, as totalconv_fwd does).
  */
 int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int lmax_sky,
                    const double* alm, double* alm_bar, void* stream);
