@@ -188,6 +188,35 @@ def test_fwd_full_size_sampled_columns(B, orc, name, ncol):
     assert g <= GATE_C
 
 
+def test_fwd_beam_rows_equal_up_to_sign(B, orc):
+    """Beam rows mb and -mb equal (s = +1), opposite (s = -1) or unrelated, mixed in one beam:
+    the forward takes the even / odd form on the first two kinds and the general form on the
+    others; every column against the oracle.  Odd ring count: the middle ring is its own
+    mirror."""
+    L, M, nring = 90, 6, 181
+    x = S.ring_cosines(nring)
+    alm = S.sky_alm(L, 61) + 0.0j
+    rng = np.random.Generator(np.random.PCG64(62))
+
+    def row(mb):
+        r = (rng.standard_normal(L + 1) + 1j * rng.standard_normal(L + 1)) / np.sqrt(2.0)
+        r[:abs(mb)] = 0.0
+        return r
+
+    blm = np.zeros((2 * M + 1, L + 1), np.complex128)
+    blm[M] = row(0)
+    for mb in range(1, M + 1):
+        blm[M + mb] = row(mb)
+        kind = mb % 3
+        blm[M - mb] = blm[M + mb] if kind == 0 else (-blm[M + mb] if kind == 1 else row(mb))
+    say(f"totalconv_fwd rows +1 / -1 / general, L={L} M={M} nring={nring}")
+    got = B.totalconv_fwd(L, M, x, dev(alm), dev(blm)).cpu().numpy()
+    ref = orc.totalconv_fwd(L, M, x, alm, blm)
+    g = column_gate(got, ref)
+    say(f"  column gate {g:.3e}")
+    assert g <= GATE_C
+
+
 def test_fwd_deterministic(B):
     w = S.WORKLOADS["small"]
     x, alm, blm = w.xring(), dev(w.alm()), dev(w.blm())
