@@ -66,7 +66,8 @@ int g_matrix_R = 0;   // rows per lane of wigner_d_matrix (tc_set_tile); 0 = bui
 tc::Tile default_tile(int op, int lmax)
 {
     // Built-in choice from a sweep at lmax 4096 / mbmax 14 on MI355X: the forward
-    // prefers 4 chains per lane (3 waves per SIMD) with 64-l blocks, the adjoint 8.
+    // prefers 4 chains per lane (3 waves per SIMD for the general form, 4 for the even /
+    // odd form) with 64-l blocks, the adjoint 8.
     tc::Tile t{4, 256, 32, 4};
     if (op == TC_OP_FWD) t = lmax >= 256 ? tc::Tile{4, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
     if (op == TC_OP_ADJ) t = lmax >= 256 ? tc::Tile{8, 256, 64, 4} : tc::Tile{2, 256, 32, 4};
