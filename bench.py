@@ -140,8 +140,23 @@ def cpu_baseline(w, x, alm, blm, G_cols_fn, seconds):
         "cores": int(oracle.max_threads()),
         "kind": "oracle",
         "sample": f"{ncols} seeded random (mb, msky) columns x all {w.nring} rings of the {w.name} "
-                  f"workload, forward + adjoint column sums, x87 long double, {elapsed:.1f} s",
+                  f"workload, forward + adjoint column sums, x87 long double, {elapsed:.1f} s; "
+                  f"{host_cpu()}",
     }
+
+
+def host_cpu():
+    """The host's CPU model and the cores this process may run on."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} cores in the process affinity set"
 
 
 def truncate_sky(S, alm, lmax_sky, lmax):
