@@ -275,7 +275,10 @@ typedef struct tc_detector {
  * released by tc_plan_destroy).  Creation is synchronous on `stream`.  The
  * pointed-to data may change between executions: each execution reads the
  * beams, sky and cotangents afresh (including, for the forward, which beam rows
- * are equal up to a sign, as totalconv_fwd does).
+ * are equal up to a sign, as totalconv_fwd does).  A forward plan also reads the
+ * beams once at creation: if every row pair b_{l,-mb} = +-b_{l,mb} then, the
+ * queue kernel is built for four waves per SIMD instead of three (a speed
+ * choice only; results do not depend on it).
  */
 int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int lmax_sky,
                    const double* alm, double* alm_bar, void* stream);

@@ -784,6 +784,7 @@ struct tc_plan_s {
     size_t dbytes = 0;
     int nitems = 0;
     int grid = 0;
+    bool rows = false;   // forward: every beam row pair equal up to a sign when the plan was made
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -942,11 +943,28 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     if (!rc) rc = (int)hipMemcpy(dm + items_off, it3.data(), sizeof(int) * it3.size(), hipMemcpyHostToDevice);
     if (rc) { destroy_plan(p); return hip_fail(rc, "plan: argument upload"); }
 
+    // ---- forward: read the beam row signs once now; if every row pair of every beam is
+    // equal up to a sign, the queue kernel is built for the even / odd form's register
+    // budget (both variants compute both forms: the signs are taken again on each execution)
+    if (op == TC_OP_FWD) {
+        bool all = true;
+        for (int i = 0; i < ndet && !rc && all; ++i) {
+            int* sym = reinterpret_cast<int*>(dm + base[i] + lay[i].sym);
+            rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, sym, stream);
+            if (!rc) rc = (int)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+            std::vector<int> h(2 * dets[i].mbmax + 1, 0);
+            if (!rc) rc = (int)hipMemcpy(h.data(), sym, sizeof(int) * h.size(), hipMemcpyDeviceToHost);
+            for (int v : h) all = all && (v != 0);
+        }
+        if (rc) { destroy_plan(p); return hip_fail(rc, "plan: beam row signs"); }
+        p->rows = all;
+    }
+
     // ---- persistent grid: every resident workgroup slot of the device
     int dev = 0, cus = 0, per_cu = 0;
     rc = (int)hipGetDevice(&dev);
     if (!rc) rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (!rc) rc = tc::queue_occupancy(op, p->tile, &per_cu);
+    if (!rc) rc = tc::queue_occupancy(op, p->tile, p->rows, &per_cu);
     if (rc || cus < 1 || per_cu < 1) { destroy_plan(p); return hip_fail(rc ? rc : 1, "plan: occupancy query"); }
     p->grid = (int)std::min<long long>((long long)cus * per_cu, std::max(nitems, 1LL));
 
@@ -963,7 +981,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
                                       reinterpret_cast<int*>(dm + base[i] + lay[i].sym), cs);
     if (!rc && op == TC_OP_FWD)
         rc = tc::launch_fwd_queue(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, counter,
-                                  p->tile, p->grid, cs);
+                                  p->tile, p->rows, p->grid, cs);
     if (!rc && op == TC_OP_ADJ) {
         rc = tc::launch_adj_queue(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items, p->nitems, counter,
                                   p->tile, p->grid, cs);

@@ -116,13 +116,13 @@ int launch_adj_epilogue(const EpiArgs& e, void* stream);
 
 // Batched (persistent) launches: items = (detector, column, tile) triples in queue order.
 int launch_reset_counter(int* counter, void* stream);
-int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, bool rows, int grid,
                      void* stream);
 int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
                      void* stream);
 int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream);
 int launch_adj_beam(const EpiArgs& e, void* stream);
-int queue_occupancy(int op, Tile t, int* blocks_per_cu);
+int queue_occupancy(int op, Tile t, bool rows, int* blocks_per_cu);
 bool tile_supported(int op, Tile t);
 
 }  // namespace tc

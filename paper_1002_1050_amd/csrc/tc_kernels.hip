@@ -608,10 +608,13 @@ __global__ void __launch_bounds__(NT, (rows_min_waves<R>())) k_fwd_rows(const Fw
 }
 
 // Persistent form: each workgroup takes (detector, column, tile) items from a
-// queue ordered longest first until it is empty.
-template <int R, int NT, int TB>
-__global__ void __launch_bounds__(NT, min_waves<R>()) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
-                                                  int nitems, int* __restrict__ counter)
+// queue ordered longest first until it is empty.  W: resident waves per SIMD asked of
+// the compiler (the general form's budget, or the even / odd form's for plans whose
+// beams had every row pair equal up to a sign when the plan was made; either variant
+// computes both forms).
+template <int R, int NT, int TB, int W>
+__global__ void __launch_bounds__(NT, W) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
+                                                     int nitems, int* __restrict__ counter)
 {
     __shared__ double4 cf[2][TB][2];
     __shared__ int next;
@@ -1091,14 +1094,19 @@ int launch_reset_counter(int* counter, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
+int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, bool rows, int grid,
                      void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-#define X(r, tb)                                                                                            \
-    if (t.R == r && t.TB == tb) {                                                                           \
-        hipLaunchKernelGGL((k_fwd_queue<r, 256, tb>), dim3(grid), dim3(256), 0, s, dets, items, nitems, counter); \
-        return (int)hipGetLastError();                                                                      \
+#define X(r, tb)                                                                                             \
+    if (t.R == r && t.TB == tb) {                                                                            \
+        if (rows)                                                                                            \
+            hipLaunchKernelGGL((k_fwd_queue<r, 256, tb, rows_min_waves<r>()>), dim3(grid), dim3(256), 0, s, dets, \
+                               items, nitems, counter);                                                      \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_fwd_queue<r, 256, tb, min_waves<r>()>), dim3(grid), dim3(256), 0, s, dets,  \
+                               items, nitems, counter);                                                      \
+        return (int)hipGetLastError();                                                                       \
     }
     TC_FWD_VARIANTS(X)
 #undef X
@@ -1129,13 +1137,16 @@ int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm
 }
 
 // Resident workgroups per CU of the persistent kernels (for sizing their grid).
-int queue_occupancy(int op, Tile t, int* blocks_per_cu)
+int queue_occupancy(int op, Tile t, bool rows, int* blocks_per_cu)
 {
     int n = 0;
     hipError_t rc = hipErrorInvalidValue;
     if (op == 1) {
-#define X(r, tb) \
-        if (t.R == r && t.TB == tb) rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb>, 256, 0);
+#define X(r, tb)                                                                                                 \
+        if (t.R == r && t.TB == tb)                                                                              \
+            rc = rows ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb, rows_min_waves<r>()>, \
+                                                                     256, 0)                                    \
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb, min_waves<r>()>, 256, 0);
         TC_FWD_VARIANTS(X)
 #undef X
     } else if (op == 2) {
