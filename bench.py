@@ -57,15 +57,15 @@ def forward_flops_per_term(w, blm, paired):
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "4164e23a646c74c722436435a281a9f65611440be0475ce417b0e5129eaa67aa",
+    "kernel_source_sha256": "36222b93fe4556b1b6cd11d7d073470a176e90a90c2b5d1342055e67178a1f64",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
         # (the forward: its two launches, k_fwd_rows and k_fwd, together)
-        "k_fwd": int((2907582.75 + 3722.625) * 1024 * (2147483648 / (1048610.375 * 1024))
-                     + (21857442.25 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5962050.9375 * 1024 * (2147483648 / (1048610.375 * 1024))
-                     + 15228209.59375 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_fwd": int((2908450.3125 + 3726.75) * 1024 * (2147483648 / (1048610.1875 * 1024))
+                     + (21856045.625 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5964126.75 * 1024 * (2147483648 / (1048610.1875 * 1024))
+                     + 15228472.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
