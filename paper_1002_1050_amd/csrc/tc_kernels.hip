@@ -33,6 +33,18 @@ constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-9
 // A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
 // (F0 <= l+1, |x - F1| < 2, F2 <= 2), which bounds growth inside a TS block.
 constexpr int GROWTH_BITS_PER_STEP = 16;
+// Scaled chains are rescaled (and folded) only every RS_STEPS steps: a rescaled chain
+// keeps max(|d|, |d_prev|) < 1, so its significand stays below 2^(16 RS_STEPS) = 2^512
+// until the next rescale, and a chain still scaled after one (true exponent below -900)
+// stays below 2^-388 until the next, where the skip test of a chain at 2^-100
+// (GROWTH_BITS_PER_STEP * TS bits of headroom) cannot fire.  Between rescales the skip
+// test looks at the plain chains only.
+constexpr int RS_STEPS = 32;
+template <int TB>
+constexpr int rs_block() { static_assert(TB % TS == 0 && (TB % RS_STEPS == 0 || RS_STEPS % TB == 0), "tile"); return TB < RS_STEPS ? TB : RS_STEPS; }
+constexpr int SKIP_EXP_MAX = -(FOLD_EXP + GROWTH_BITS_PER_STEP * RS_STEPS) - GROWTH_BITS_PER_STEP * TS;  // 260
+static_assert(RS_STEPS % TS == 0 && GROWTH_BITS_PER_STEP * RS_STEPS < 1023 && SKIP_EXP_MAX >= 100,
+              "rescale period: no overflow of a scaled significand, no missed hot chain at skip 2^-100");
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
@@ -190,6 +202,18 @@ __device__ __forceinline__ bool lane_may_be_hot(const double (&d)[R], const doub
     double m = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) m = fmax(m, fmax(fabs(d[r]), fabs(dp[r])));
+    return m >= thr;
+}
+
+// The same test between two rescales, while some chains are still scaled: those
+// cannot be hot yet (see RS_STEPS), and their d is in scaled units, so they are left out.
+template <int R>
+__device__ __forceinline__ bool lane_may_be_hot_plain(const double (&d)[R], const double (&dp)[R],
+                                                      const int (&E)[R], double thr)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) m = fmax(m, E[r] == 0 ? fmax(fabs(d[r]), fabs(dp[r])) : 0.0);
     return m >= thr;
 }
 
@@ -500,6 +524,7 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
         stage_block<NC, NP>(a, raw, l0 + st0, mb, ms, cf[0][st0]);
     }
     __syncthreads();
+    constexpr int RS_BLK = rs_block<TB>();   // steps between rescales of scaled chains
     const int nblk = (L - l0) / TB + 1;
     for (int kb = 0; kb < nblk; ++kb) {
         const int buf = kb & 1;
@@ -510,13 +535,13 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
 #pragma unroll
             for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, lb + TB + st, mb, ms);
         }
-        for (int s0 = 0; s0 < TB; s0 += TS) {
+        for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
             if (scaled) {
-                bool any = false, hot = false;
+                bool any = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     int k;
-                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
+                    (void)check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
                     if (acc_on) {   // sums in the chain's scaled units follow it
 #pragma unroll
                         for (int c = 0; c < NC; ++c) {
@@ -527,16 +552,17 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
                     any |= (E[r] < 0);
                 }
                 scaled = wave_any(any);
-                if (!acc_on) acc_on = wave_any(hot);
-            } else if (!acc_on) {
-                acc_on = wave_any(lane_may_be_hot<R>(d, dp, thr));
             }
-            if (!acc_on)
-                fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
-            else if constexpr (ROWS)
-                fwd_steps_rows<R, true>(cf[buf], s0, x, d, dp, c1r[0], c1i[0], c2r[0], c2i[0]);
-            else
-                fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+            for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
+                if (!acc_on)
+                    acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
+                if (!acc_on)
+                    fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                else if constexpr (ROWS)
+                    fwd_steps_rows<R, true>(cf[buf], s0, x, d, dp, c1r[0], c1i[0], c2r[0], c2i[0]);
+                else
+                    fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+            }
         }
         if (stage) stage_block<NC, NP>(a, raw, lb + TB + st, mb, ms, cf[buf ^ 1][st]);
         __syncthreads();
@@ -747,26 +773,27 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         sh_.cf[0][st0] = make_double4(A, nB, F2, 0.0);
     }
     __syncthreads();
+    constexpr int RS_BLK = rs_block<TB>();   // steps between rescales of scaled chains
     const int nblk = (L - l0) / TB + 1;
     for (int kb = 0; kb < nblk; ++kb) {
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
-        for (int s0 = 0; s0 < TB; s0 += TS) {
-            if (scaled) {
-                bool any = false, hot = false;
+        for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
+          if (scaled) {
+              bool any = false;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const bool was = E[r] < 0;
-                    int k;
-                    hot |= check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
-                    if (was && E[r] == 0) load_g(r);
-                    any |= (E[r] < 0);
-                }
-                scaled = wave_any(any);
-                if (!acc_on) acc_on = wave_any(hot);
-            } else if (!acc_on) {
-                acc_on = wave_any(lane_may_be_hot<R>(d, dp, thr));
-            }
+              for (int r = 0; r < R; ++r) {
+                  const bool was = E[r] < 0;
+                  int k;
+                  (void)check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
+                  if (was && E[r] == 0) load_g(r);
+                  any |= (E[r] < 0);
+              }
+              scaled = wave_any(any);
+          }
+          for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
+            if (!acc_on)
+                acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
             if (acc_on) {
                 for (int h = 0; h < TS; h += TR) {
                     // the group's coefficients are read before its first lane-sum store, so
@@ -828,6 +855,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 }
                 if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
             }
+          }
         }
         const int st = stage_slot<NT, TB>(tid, kb + 1);
         if (st >= 0 && kb + 1 < nblk) {
