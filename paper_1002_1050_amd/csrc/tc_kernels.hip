@@ -5,6 +5,9 @@
 // Mapping.  A workgroup owns one (mb, msky) column and NT*R ring slots of it;
 // each lane walks R chains (one per ring slot) up in l, in lock-step, so the
 // per-l recursion coefficients and weights are uniform across the workgroup.
+// A lane takes R consecutive slots and a wave 64 R (slots run from the pole to
+// the equator), so that the chains of a wave share their regime: all still below
+// the skip threshold, or not, over the same stretch of l.
 // They are built per block of TB values of l in LDS (double-buffered: the next
 // block is prepared while the current one is consumed) and read back as
 // broadcasts.  A ring slot is either a mirror pair (beta, pi - beta) -- one
@@ -15,7 +18,7 @@
 // as a logarithm in double-double (Sec. 3.2 eq. logstart) and split into a
 // significand and a power of two.  While a chain's value is below 2^-900 it is
 // carried as d * 2^E with E < 0 and renormalised by exact powers of two every
-// TS steps; once it reaches 2^-900 it is folded into a plain double (E = 0),
+// RS_STEPS steps; once it reaches 2^-900 it is folded into a plain double (E = 0),
 // as Sec. 3.2 prescribes.  The checks are wave-uniform branches, so the inner
 // loop has no per-step branches.
 
@@ -494,7 +497,7 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
     int E[R], jd[R], jm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int s = tile * (NT * R) + r * NT + tid;
+        const int s = tile * (NT * R) + tid * R + r;   // a wave: 64 R consecutive ring pairs
         jd[r] = -1; jm[r] = -1;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
 #pragma unroll
@@ -729,7 +732,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     int E[R], jd[R], jm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int s = tile * (NT * R) + r * NT + tid;
+        const int s = tile * (NT * R) + tid * R + r;   // a wave: 64 R consecutive ring pairs
         jd[r] = -1; jm[r] = -1;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
         g1r[r] = 0.0; g1i[r] = 0.0; g2r[r] = 0.0; g2i[r] = 0.0;
@@ -779,83 +782,83 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
         for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
-          if (scaled) {
-              bool any = false;
+            if (scaled) {
+                bool any = false;
 #pragma unroll
-              for (int r = 0; r < R; ++r) {
-                  const bool was = E[r] < 0;
-                  int k;
-                  (void)check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
-                  if (was && E[r] == 0) load_g(r);
-                  any |= (E[r] < 0);
-              }
-              scaled = wave_any(any);
-          }
-          for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
-            if (!acc_on)
-                acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
-            if (acc_on) {
-                for (int h = 0; h < TS; h += TR) {
-                    // the group's coefficients are read before its first lane-sum store, so
-                    // the reads are in flight together instead of one round trip per step
-                    double4 kk[TR];
+                for (int r = 0; r < R; ++r) {
+                    const bool was = E[r] < 0;
+                    int k;
+                    (void)check_chain(d[r], dp[r], E[r], a.skip_exp, true, k);
+                    if (was && E[r] == 0) load_g(r);
+                    any |= (E[r] < 0);
+                }
+                scaled = wave_any(any);
+            }
+            for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
+                if (!acc_on)
+                    acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
+                if (acc_on) {
+                    for (int h = 0; h < TS; h += TR) {
+                        // the group's coefficients are read before its first lane-sum store, so
+                        // the reads are in flight together instead of one round trip per step
+                        double4 kk[TR];
 #pragma unroll
-                    for (int t = 0; t < TR; ++t) kk[t] = sh_.cf[buf][s0 + h + t];
+                        for (int t = 0; t < TR; ++t) kk[t] = sh_.cf[buf][s0 + h + t];
 #pragma unroll
-                    for (int t = 0; t < TR; ++t) {
-                        const double4 k = kk[t];
-                        double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+                        for (int t = 0; t < TR; ++t) {
+                            const double4 k = kk[t];
+                            double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                p1r = fma(d[r], g1r[r], p1r);
+                                p1i = fma(d[r], g1i[r], p1i);
+                                p2r = fma(d[r], g2r[r], p2r);
+                                p2i = fma(d[r], g2i[r], p2i);
+                                const double u = fma(x[r], k.x, k.y);
+                                const double dn = fma(-k.z, dp[r], u * d[r]);
+                                dp[r] = d[r];
+                                d[r] = dn;
+                            }
+                            const int wpos = (lane / PER) * CH + lane % PER;
+                            sh_.red[wave][4 * t + 0][wpos] = p1r;
+                            sh_.red[wave][4 * t + 1][wpos] = p1i;
+                            sh_.red[wave][4 * t + 2][wpos] = p2r;
+                            sh_.red[wave][4 * t + 3][wpos] = p2i;
+                        }
+                        wave_lds_sync();
+                        // lane -> value o = 4 t + c, part sub of GL; adds PER consecutive lane sums
+                        const int o = lane / GL, sub = lane - o * GL;
+                        const double* src = &sh_.red[wave][o][sub * CH];
+                        // all reads in flight at once, then a fixed binary tree
+                        double part[PER];
+#pragma unroll
+                        for (int i = 0; i < PER; ++i) part[i] = src[i];
+#pragma unroll
+                        for (int w2 = 1; w2 < PER; w2 <<= 1) {
+#pragma unroll
+                            for (int i = 0; i < PER; i += 2 * w2) part[i] += part[i + w2];
+                        }
+                        double v = part[0];
+                        if (GL >= 2) v += quad_xor<1>(v);
+                        if (GL >= 4) v += quad_xor<2>(v);
+                        if (sub == 0) sh_.wsum[buf][wave][s0 + h + (o >> 2)][o & 3] = v;
+                        wave_lds_sync();
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TS; ++t) {
+                        const double4 k = sh_.cf[buf][s0 + t];
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            p1r = fma(d[r], g1r[r], p1r);
-                            p1i = fma(d[r], g1i[r], p1i);
-                            p2r = fma(d[r], g2r[r], p2r);
-                            p2i = fma(d[r], g2i[r], p2i);
                             const double u = fma(x[r], k.x, k.y);
                             const double dn = fma(-k.z, dp[r], u * d[r]);
                             dp[r] = d[r];
                             d[r] = dn;
                         }
-                        const int wpos = (lane / PER) * CH + lane % PER;
-                        sh_.red[wave][4 * t + 0][wpos] = p1r;
-                        sh_.red[wave][4 * t + 1][wpos] = p1i;
-                        sh_.red[wave][4 * t + 2][wpos] = p2r;
-                        sh_.red[wave][4 * t + 3][wpos] = p2i;
                     }
-                    wave_lds_sync();
-                    // lane -> value o = 4 t + c, part sub of GL; adds PER consecutive lane sums
-                    const int o = lane / GL, sub = lane - o * GL;
-                    const double* src = &sh_.red[wave][o][sub * CH];
-                    // all reads in flight at once, then a fixed binary tree
-                    double part[PER];
-#pragma unroll
-                    for (int i = 0; i < PER; ++i) part[i] = src[i];
-#pragma unroll
-                    for (int w2 = 1; w2 < PER; w2 <<= 1) {
-#pragma unroll
-                        for (int i = 0; i < PER; i += 2 * w2) part[i] += part[i + w2];
-                    }
-                    double v = part[0];
-                    if (GL >= 2) v += quad_xor<1>(v);
-                    if (GL >= 4) v += quad_xor<2>(v);
-                    if (sub == 0) sh_.wsum[buf][wave][s0 + h + (o >> 2)][o & 3] = v;
-                    wave_lds_sync();
+                    if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
                 }
-            } else {
-#pragma unroll
-                for (int t = 0; t < TS; ++t) {
-                    const double4 k = sh_.cf[buf][s0 + t];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const double u = fma(x[r], k.x, k.y);
-                        const double dn = fma(-k.z, dp[r], u * d[r]);
-                        dp[r] = d[r];
-                        d[r] = dn;
-                    }
-                }
-                if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
             }
-          }
         }
         const int st = stage_slot<NT, TB>(tid, kb + 1);
         if (st >= 0 && kb + 1 < nblk) {
