@@ -556,6 +556,8 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
                 }
                 scaled = wave_any(any);
             }
+            // kept rolled: unrolled, the 4-wave forward spills twice as many registers
+#pragma unroll 1
             for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
                 if (!acc_on)
                     acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
