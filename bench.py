@@ -57,15 +57,15 @@ def forward_flops_per_term(w, blm, paired):
 # reads for a device-to-device copy of known size in the same run.  Valid only for
 # the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "36222b93fe4556b1b6cd11d7d073470a176e90a90c2b5d1342055e67178a1f64",
+    "kernel_source_sha256": "a7ca3ab2602f5f869d32fe4129db00f1e1678102608b6182945023e5a6ae9fc8",
     "lmax4096": {
         # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
         #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        # (the forward: its two launches, k_fwd_rows and k_fwd, together)
-        "k_fwd": int((2908450.3125 + 3726.75) * 1024 * (2147483648 / (1048610.1875 * 1024))
-                     + (21856045.625 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5964126.75 * 1024 * (2147483648 / (1048610.1875 * 1024))
-                     + 15228472.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        # (the forward at R 4: its two launches, k_fwd_rows and k_fwd, together)
+        "k_fwd": int((2969559.0625 + 3722.5) * 1024 * (2147483648 / (1048610.0 * 1024))
+                     + (21857529.1875 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
+        "k_adj": int(5953641.8125 * 1024 * (2147483648 / (1048610.0 * 1024))
+                     + 15227947.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
     },
 }
 
