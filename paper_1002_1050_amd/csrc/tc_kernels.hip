@@ -806,6 +806,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                         double4 kk[TR];
 #pragma unroll
                         for (int t = 0; t < TR; ++t) kk[t] = sh_.cf[buf][s0 + h + t];
+                        __builtin_amdgcn_s_setprio(0);   // steps: normal issue priority
 #pragma unroll
                         for (int t = 0; t < TR; ++t) {
                             const double4 k = kk[t];
@@ -828,6 +829,10 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                             sh_.red[wave][4 * t + 3][wpos] = p2i;
                         }
                         wave_lds_sync();
+                        // the reduction is a chain of dependent LDS reads, adds and DPP moves with
+                        // little work: raised priority lets it issue as soon as each operand is in,
+                        // ahead of the other wave's steps, up to the next group's coefficient reads
+                        __builtin_amdgcn_s_setprio(1);
                         // lane -> value o = 4 t + c, part sub of GL; adds PER consecutive lane sums
                         const int o = lane / GL, sub = lane - o * GL;
                         const double* src = &sh_.red[wave][o][sub * CH];
