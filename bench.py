@@ -54,30 +54,35 @@ def forward_flops_per_term(w, blm, paired):
 
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over
 # this bench (the kernels' dispatches at lmax 4096), each counter scaled by what it
-# reads for a device-to-device copy of known size in the same run.  Valid only for
-# the kernel source they were taken on (SHA-256 of tc_kernels.hip); otherwise null.
+# reads for a device-to-device copy of known size in the same run, per kernel and tile
+# (R, TB, TR).  Valid only for the kernel source they were taken on (SHA-256 of
+# tc_kernels.hip) and the tile the bench runs; otherwise null.
+def _bytes(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib=2097152.0):
+    """FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes) + the same for WRITE_SIZE."""
+    return int(fetch_kib * 1024 * (2147483648 / (copy_fetch_kib * 1024))
+               + write_kib * 1024 * (2147483648 / (copy_write_kib * 1024)))
+
+
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "a7ca3ab2602f5f869d32fe4129db00f1e1678102608b6182945023e5a6ae9fc8",
+    "kernel_source_sha256": "a537dd428143d0bb5a6b0651adda6b2054b7fa5353d1b3eea03d611d3c970e61",
     "lmax4096": {
-        # bytes = FETCH_SIZE KiB x 1024 x (2 GiB / copy's FETCH_SIZE bytes)
-        #       + WRITE_SIZE KiB x 1024 x (2 GiB / copy's WRITE_SIZE bytes)
-        # (the forward at R 4: its two launches, k_fwd_rows and k_fwd, together)
-        "k_fwd": int((2969559.0625 + 3722.5) * 1024 * (2147483648 / (1048610.0 * 1024))
-                     + (21857529.1875 + 0.0) * 1024 * (2147483648 / (2097152.0 * 1024))),
-        "k_adj": int(5953641.8125 * 1024 * (2147483648 / (1048610.0 * 1024))
-                     + 15227947.125 * 1024 * (2147483648 / (2097152.0 * 1024))),
+        # the forward: its two launches, k_fwd_rows and k_fwd, together
+        "k_fwd": {"4,64,4": _bytes(2968655.5625 + 3722.5, 21857908.0625 + 0.0, 1048612.25),
+                  "8,64,4": _bytes(1316486.6875 + 3718.5, 15350518.65625 + 0.0, 1048611.6875)},
+        "k_adj": {"8,64,4": _bytes(5949830.5625, 15227927.84375, 1048612.25),
+                  "8,32,4": _bytes(5953789.8125, 15225733.03125, 1048611.6875)},
     },
 }
 
 
-def hbm_traffic(kernel, workload):
+def hbm_traffic(kernel, workload, tile):
     import hashlib
     src = os.path.join(ROOT, "paper_1002_1050_amd", "csrc", "tc_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if sha != MEASURED_TRAFFIC["kernel_source_sha256"]:
         return None
-    return MEASURED_TRAFFIC.get(workload, {}).get(kernel)
+    return MEASURED_TRAFFIC.get(workload, {}).get(kernel, {}).get(",".join(str(int(v)) for v in tile))
 
 
 def parse():
@@ -451,7 +456,7 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": hbm_traffic(dom_name, w.name),
+        "traffic": hbm_traffic(dom_name, w.name, ta if dom_name == "k_adj" else tf),
         "flops_per_term": fpt,
         "terms_per_launch": terms,
         "launch_ms": round(dom_ms, 3),
