@@ -64,7 +64,10 @@ def _bytes(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib=2097152.0):
 
 
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "a537dd428143d0bb5a6b0651adda6b2054b7fa5353d1b3eea03d611d3c970e61",
+    # taken on the first source; the second differs from it in comments only (its
+    # generated device code is identical, instruction for instruction)
+    "kernel_source_sha256": ["a537dd428143d0bb5a6b0651adda6b2054b7fa5353d1b3eea03d611d3c970e61",
+                             "1cef31ea1cf8a60a8ac887097cc2f1af48d2674a98e2eae30acacf3691ddc3a0"],
     "lmax4096": {
         # the forward: its two launches, k_fwd_rows and k_fwd, together
         "k_fwd": {"4,64,4": _bytes(2968655.5625 + 3722.5, 21857908.0625 + 0.0, 1048612.25),
@@ -80,7 +83,7 @@ def hbm_traffic(kernel, workload, tile):
     src = os.path.join(ROOT, "paper_1002_1050_amd", "csrc", "tc_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != MEASURED_TRAFFIC["kernel_source_sha256"]:
+    if sha not in MEASURED_TRAFFIC["kernel_source_sha256"]:
         return None
     return MEASURED_TRAFFIC.get(workload, {}).get(kernel, {}).get(",".join(str(int(v)) for v in tile))
 

@@ -31,7 +31,7 @@ namespace {
 
 // Tile parameters (template arguments): R chains per lane, NT lanes per workgroup,
 // TB values of l per coefficient block, TR steps per wave reduction (adjoint).
-constexpr int TS = 8;         // steps between scale / skip checks
+constexpr int TS = 8;         // steps between skip checks
 constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-900
 // A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
 // (F0 <= l+1, |x - F1| < 2, F2 <= 2), which bounds growth inside a TS block.
@@ -225,12 +225,14 @@ __device__ __forceinline__ double hot_threshold(int skip_exp)
     return ldexp(1.0, -skip_exp - GROWTH_BITS_PER_STEP * TS);
 }
 
-// One scale / skip check of a chain, every TS steps.  From the exponent e of
-// max(|d|, |d_prev|) it takes the true exponent te = E + e of the chain.
+// One scale check of a chain (every RS_STEPS steps in the convolution walks, every
+// TS steps where each d is written out).  From the exponent e of max(|d|, |d_prev|)
+// it takes the true exponent te = E + e of the chain.
 //  - rescale: a scaled chain (E < 0) is folded into plain doubles once te reaches
 //    -900 (k = E), otherwise brought back to a significand near 1 (k = -e); the
 //    power of two k applied to (d, d_prev) is returned for the caller's sums.
-//  - returns whether |d| may reach 2^-skip_exp within the next TS steps.
+//  - returns whether |d| may reach 2^-skip_exp within the next TS steps (the walks
+//    take that test from the plain chains' magnitudes instead, every TS steps).
 // Branch-free per chain; the callers' conditions are wave-uniform.
 __device__ __forceinline__ bool check_chain(double& d, double& dp, int& E, int skip_exp, bool rescale, int& k)
 {
