@@ -203,19 +203,23 @@ def test_batched16_full_size_sampled(B, orc):
     assert worst <= 1e-11
 
 
-def test_plan_follows_beams_changed_between_executions(B):
-    """Beams edited in place between executions of one plan: first with rows mb and -mb equal
-    up to a sign (the even / odd form), then general complex rows, then the first beams again.
-    Every execution equals a plain call on the current beams bit for bit."""
+@pytest.mark.parametrize("first", ["sym", "gen"])
+def test_plan_follows_beams_changed_between_executions(B, first):
+    """Beams edited in place between executions of one plan.  The plan is made with beams whose
+    rows mb and -mb are equal up to a sign (its queue kernel then takes the even / odd form's
+    register budget) or with general complex rows (the general budget), and executed on the two
+    kinds in turn.  Every execution equals a plain call on the current beams bit for bit."""
     L, M, x = 150, 6, S.ring_cosines(300)
     alm = dev(S.sky_alm(L, 91))
     sym = [S.beam_blm(L, M, 40.0, 0.25), S.beam_blm(L, M, 20.0, 0.1)]
     gen = [S.random_beam(L, M, 92), S.random_beam(L, M, 93)]
+    order = (sym, gen, sym) if first == "sym" else (gen, sym, gen)
     dets = [{"lmax": L, "mbmax": M, "cosbeta": x, "blm": dev(b),
-             "C": torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda")} for b in sym]
+             "C": torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda")}
+            for b in order[0]]
     plan = B.Plan(B.TC_OP_FWD, dets, L, alm)
     try:
-        for beams in (sym, gen, sym):
+        for beams in order:
             for d, b in zip(dets, beams):
                 d["blm"].copy_(dev(b))
                 d["C"].fill_(float("nan"))
@@ -226,4 +230,4 @@ def test_plan_follows_beams_changed_between_executions(B):
                 assert torch.equal(plain, d["C"]), "plan result differs from the plain call"
     finally:
         plan.close()
-    say("plan follows in-place beam changes")
+    say(f"plan made on {first} beams follows in-place beam changes")
