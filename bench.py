@@ -248,6 +248,80 @@ def batched_compare(reps, tune):
         "reps": reps,
     }
     plan.close()
+    torch.cuda.empty_cache()
+    res["adjoint"] = batched_adjoint_compare(w, dets, plain, alm, reps, tune)
+    return res
+
+
+def batched_adjoint_compare(w, dets, plain, alm, reps, tune):
+    """The adjoint of the same sixteen detectors, each forward output C as its cotangent: sixteen
+    plain totalconv_adj calls (each with its own tile), each detector's sky gradient added into
+    the full one, against one tc_plan_execute of the adjoint plan at its built-in tile (the plan
+    sums the sky gradients in its graph).  Interleaved repetitions."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import autotune
+    from paper_1002_1050_amd import synthetic as S
+    dev = alm.device
+    adets = [{"lmax": d["lmax"], "mbmax": d["mbmax"], "cosbeta": d["cosbeta"], "blm": d["blm"],
+              "Cbar": d["C"], "blm_bar": torch.empty_like(d["blm"])} for d in dets]
+    alm_bar = torch.empty_like(alm)
+    plain_bar = torch.zeros_like(alm)
+    legs = []
+    for d, x, a_d, blm, C, _ in plain:
+        # full-layout positions of the detector's truncated sky (m-major, l inner)
+        ix = np.concatenate([np.arange(S.alm_index(w.lmax, m, m), S.alm_index(w.lmax, d.lmax, m) + 1)
+                             for m in range(d.lmax + 1)])
+        t = autotune.tune_plain(B.TC_OP_ADJ, d.lmax, d.mbmax, x, a_d, blm, C, reps=1) if tune else (0, 0, 0)
+        legs.append((d, x, a_d, blm, C, t, torch.from_numpy(ix).to(dev)))
+        log(f"  adjoint detector lmax={d.lmax} mbmax={d.mbmax} plain tile (R, TB, TR)={t}")
+
+    def run_plain():
+        plain_bar.zero_()
+        for d, x, a_d, blm, C, t, ix in legs:
+            B.set_tile_ex(B.TC_OP_ADJ, *t)
+            ab, _ = B.totalconv_adj(d.lmax, d.mbmax, x, a_d, blm, C)
+            plain_bar.index_add_(0, ix, ab)
+        B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
+
+    # the plan keeps its built-in tile: its partial sums grow as 1/R (about 50 GB at R 8 for these
+    # sixteen detectors), and a tuning trial at R 2 would need about 150 GB of them
+    plan = B.Plan(B.TC_OP_ADJ, adets, w.lmax, alm, alm_bar)
+    s = torch.cuda.current_stream(dev)
+    run_plain()
+    plan.execute()
+    torch.cuda.synchronize()
+    tp, tb = [], []
+    for i in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(s)
+        run_plain()
+        e[1].record(s)
+        torch.cuda.synchronize()
+        e[2].record(s)
+        plan.execute()
+        e[3].record(s)
+        torch.cuda.synchronize()
+        tp.append(e[0].elapsed_time(e[1]))
+        tb.append(e[2].elapsed_time(e[3]))
+        log(f"  adjoint rep {i + 1}/{reps}: plain {tp[-1]:.1f} ms, batched {tb[-1]:.1f} ms")
+    ratios = [a / b for a, b in zip(tp, tb)]
+    terms = w.terms()
+    res = {
+        "workload": "the same sixteen detectors, adjoint (sky gradient summed over detectors, beam "
+                    "gradient per detector), each forward output as its cotangent",
+        "plain_ms_median": float(np.median(tp)),
+        "batched_ms_median": float(np.median(tb)),
+        "plain_terms_per_s": terms / (np.median(tp) * 1e-3),
+        "batched_terms_per_s": terms / (np.median(tb) * 1e-3),
+        "speedup_median": float(np.median(ratios)),
+        "speedup_min": float(np.min(ratios)),
+        "speedup_max": float(np.max(ratios)),
+        "plan_tile": "built-in",
+        "plan_R": plan.tile,
+        "reps": reps,
+    }
+    plan.close()
     return res
 
 
