@@ -9,8 +9,11 @@ and beam, inputs resident in HBM before timing).  `value` counts the
 
 Prints one JSON line.  Also reports, for the dominant kernel, its algorithmic
 FP64 rate against the vector-FP64 peak (HIP events around each launch on the
-stream it runs on), and the CPU oracle timed on a bounded sample of the same
-workload.
+stream it runs on) and its HBM bytes per launch (rocprofv3 counters recorded
+for this kernel source and tile), the CPU oracle timed on a bounded sample of
+the same workload, and side legs: the sixteen-detector batched plan against
+sixteen plain calls (forward and adjoint), the polarised forward, the data cube
+and the fixed-l Wigner matrix.
 """
 import argparse
 import json
