@@ -252,7 +252,13 @@ def batched_compare(reps, tune):
     }
     plan.close()
     torch.cuda.empty_cache()
-    res["adjoint"] = batched_adjoint_compare(w, dets, plain, alm, reps, tune)
+    try:
+        res["adjoint"] = batched_adjoint_compare(w, dets, plain, alm, reps, tune)
+    except Exception as e:   # noqa: BLE001 - reported in the JSON line; the forward leg stands
+        log(f"batched adjoint comparison failed: {type(e).__name__}: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        res["adjoint"] = {"error": f"{type(e).__name__}: {e}"}
     return res
 
 
@@ -573,12 +579,23 @@ def main():
         "roofline": roofline,
         "tiles_R_TB_TR": tiles,
     }
+    def side_leg(name, fn, *a):
+        """A side measurement that raises (say, short of device memory on a shared board) is
+        recorded as an error; the step's own line above is already complete."""
+        try:
+            return fn(*a)
+        except Exception as e:   # noqa: BLE001 - reported in the JSON line, never swallowed silently
+            log(f"{name} failed: {type(e).__name__}: {e}")
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            return {"error": f"{type(e).__name__}: {e}"}
+
     if args.cube_reps > 0:
         log("data cube")
-        result["datacube"] = datacube_timing(w, C, args.cube_reps)
+        result["datacube"] = side_leg("data cube", datacube_timing, w, C, args.cube_reps)
     if args.matrix_reps > 0:
         log("full matrix")
-        result["matrix"] = matrix_timing(w, args.matrix_reps)
+        result["matrix"] = side_leg("full matrix", matrix_timing, w, args.matrix_reps)
     if args.cpu_seconds > 0:
         nring = w.nring
         Gc = G.reshape(-1, nring)
@@ -596,13 +613,14 @@ def main():
         del C
         torch.cuda.empty_cache()
         log("polarised forward")
-        result["polarised"] = polarised_compare(w, x, alm, blm, args.pol_reps, not args.no_tune)
+        result["polarised"] = side_leg("polarised forward", polarised_compare, w, x, alm, blm, args.pol_reps,
+                                       not args.no_tune)
         C = None
     if args.batched_reps > 0:
         del C, G
         torch.cuda.empty_cache()
         log("batched sixteen-detector comparison")
-        result["batched"] = batched_compare(args.batched_reps, not args.no_tune)
+        result["batched"] = side_leg("batched comparison", batched_compare, args.batched_reps, not args.no_tune)
     print(json.dumps(result), flush=True)
 
 
