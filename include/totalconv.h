@@ -128,8 +128,10 @@ int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d,
  * Total-convolution coefficients (Sec. 4.1, eq. convdef):
  *   C_{mb,msky}(beta_j) = sum_{l=l0}^{lmax} conj(b_{l,mb}) d^l_{mb,msky}(beta_j) s_{l,msky}.
  * Terms whose |d| stays below 2^-100 (about the paper's 1e-30) before the first
- * crossing of that threshold within a 64-lane group of rings may be left out of
- * the sum (Sec. 4.2.1); the recursion itself always runs over every l.  A ring and
+ * crossing of that threshold within a group of rings (the 64*R consecutive ring
+ * slots, mirror pairs or single rings, that one wavefront walks; R is the tile's
+ * chains per lane) may be left out of the sum (Sec. 4.2.1); the recursion itself
+ * always runs over every l.  The same holds for totalconv_adj.  A ring and
  * its mirror ring pi - beta share one recursion (Sec. 4.2.3); on columns whose beam rows
  * mb and -mb are equal up to a sign for every l >= |mb| (read on the device each call),
  * the two rings' sums are formed from the sums over even and over odd l, which changes
