@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libtotalconv.so")
 TC_OP_WIGNER, TC_OP_FWD, TC_OP_ADJ, TC_OP_FWD_POL, TC_OP_CUBE, TC_OP_MATRIX = 0, 1, 2, 3, 4, 5
 TC_POL_SEPARATE, TC_POL_SUM = 0, 1
 TC_LMAX_LIMIT = 16384
+TC_OK, TC_EINVAL, TC_EHIP, TC_ENOMEM, TC_EUNSUPPORTED = 0, -1, -2, -3, -4   # include/totalconv.h
 
 _lib = None
 _lock = threading.Lock()

@@ -52,6 +52,20 @@ def _store(cache):
         pass
 
 
+def _out_of_memory(e):
+    """A device allocation that failed: torch's out-of-memory error or the library's TC_ENOMEM."""
+    import torch
+    return isinstance(e, torch.cuda.OutOfMemoryError) or (
+        isinstance(e, B.TotalConvError) and e.code == B.TC_ENOMEM)
+
+
+def _release():
+    import torch
+    B.workspace_cache.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def _time(fn, reps=2):
     import torch
     fn()
@@ -84,15 +98,22 @@ def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=
     try:
         for t in CANDIDATES[op]:
             B.set_tile_ex(op, *t)
-            if op == B.TC_OP_FWD:
-                times[t] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
-            elif op == B.TC_OP_FWD_POL:   # alm, blm: lists of pairs; separate outputs
-                times[t] = _time(lambda: B.totalconv_fwd_pol(lmax, mbmax, cosbeta, alm, blm), reps)
-            else:
-                B.workspace_cache.clear()
-                times[t] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
+            try:
+                if op == B.TC_OP_FWD:
+                    times[t] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
+                elif op == B.TC_OP_FWD_POL:   # alm, blm: lists of pairs; separate outputs
+                    times[t] = _time(lambda: B.totalconv_fwd_pol(lmax, mbmax, cosbeta, alm, blm), reps)
+                else:
+                    B.workspace_cache.clear()
+                    times[t] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
+            except Exception as e:   # noqa: BLE001 - only a tile that does not fit in memory is skipped
+                if not _out_of_memory(e):
+                    raise
+                _release()
     finally:
         B.set_tile_ex(op, 0, 0, 0)
+    if not times:
+        raise MemoryError(f"no tile of op {op} fits in device memory at lmax {lmax}, mbmax {mbmax}")
     best = min(times, key=times.get)
     cache = _load()
     cache[key] = {"tile": list(best), "ms": {_key(k): v for k, v in times.items()}, "default": list(default)}
@@ -110,11 +131,19 @@ def tune_plan(op, make_plan, reps=2, use_cache=True, key_extra=""):
     try:
         for t in CANDIDATES[op]:
             B.set_tile_ex(op, *t)
-            plan = make_plan()
+            try:
+                plan = make_plan()
+            except Exception as e:   # noqa: BLE001 - only a plan that does not fit is skipped
+                if not _out_of_memory(e):
+                    raise
+                _release()
+                continue
             times[t] = _time(plan.execute, reps)
             plan.close()
     finally:
         B.set_tile_ex(op, 0, 0, 0)
+    if not times:
+        raise MemoryError(f"no tile of plan op {op} fits in device memory")
     best = min(times, key=times.get)
     cache = _load()
     cache[key] = {"tile": list(best), "ms": {_key(k): v for k, v in times.items()}}

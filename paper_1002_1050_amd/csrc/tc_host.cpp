@@ -872,7 +872,11 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     p->dbytes = off;
     p->nitems = (int)nitems;
     int rc = (int)hipMalloc(&p->dmem, p->dbytes);
-    if (rc) { destroy_plan(p); return fail(TC_ENOMEM, "plan: hipMalloc of %zu bytes failed", off); }
+    if (rc) {
+        (void)hipGetLastError();   // the failed allocation must not be reported by the next launch check
+        destroy_plan(p);
+        return fail(TC_ENOMEM, "plan: hipMalloc of %zu bytes failed", off);
+    }
     char* dm = static_cast<char*>(p->dmem);
 
     // ---- tables, argument records, items (host image of everything up to the U/V gaps)

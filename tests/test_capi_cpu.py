@@ -185,3 +185,16 @@ def test_cube_chunk_setting(L):
     assert L.totalconv_datacube_workspace_bytes(20, 3, 17, 7, 64) < full
     assert L.tc_set_tile_ex(4, 3, 32, 0) == -1
     assert L.tc_set_tile(4, 0) == 0 and L.totalconv_datacube_workspace_bytes(20, 3, 17, 7, 64) == full
+
+
+def test_binding_constants_match_the_header():
+    """Every TC_* integer constant that the Python binding names has the header's value."""
+    from paper_1002_1050_amd import _binding as B
+    text = open(os.path.join(ROOT, "include", "totalconv.h")).read()
+    defines = {m.group(1): int(m.group(2)) for m in
+               re.finditer(r"#define\s+(TC_[A-Z_0-9]+)\s+\(?(-?\d+)\)?", text)}
+    named = [n for n in dir(B) if n.startswith("TC_") and isinstance(getattr(B, n), int)]
+    assert {"TC_ENOMEM", "TC_OP_ADJ", "TC_LMAX_LIMIT"} <= set(named)
+    for n in named:
+        assert n in defines, f"{n} is not defined in include/totalconv.h"
+        assert getattr(B, n) == defines[n], n
