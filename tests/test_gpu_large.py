@@ -8,10 +8,12 @@ detectors) on one full chunk:
   oracle over all 4096 rings (per-column gate 1e-11, widened by the epsilon skip's own bound
   for columns that are cold on every ring of the chunk), and the plain call bitwise equal to
   the plan on detector 0;
-* adjoint, equatorial chunk, with a seeded Gaussian cotangent: sampled rows of the summed sky
-  gradient against the oracle (every mb and ring of those msky rows, 1e-11), and the
-  dot-product identities <G, C> = <sky_bar, a> (all detectors) and <G_d, C_d> = <b_d, beam_bar_d>
-  (each detector; a property that holds at any size) for the beam gradients.
+* adjoint, on the equatorial and on the polar chunk, with a seeded Gaussian cotangent: sampled
+  rows of the summed sky gradient against the oracle (every mb and ring of those msky rows,
+  1e-11; on the polar chunk rows whose chains start deep below 2^-900 and fold during the walk),
+  and the dot-product identities <G, C> = <sky_bar, a> (all detectors) and
+  <G_d, C_d> = <b_d, beam_bar_d> (each detector; a property that holds at any size) for the beam
+  gradients.
 """
 import sys
 
@@ -150,9 +152,18 @@ def test_large4_batched_forward_polar_chunk(B, orc, inputs):
     assert worst <= GATE
 
 
-def test_large4_batched_adjoint_equatorial_chunk(B, orc, inputs):
+# msky rows of the summed sky gradient checked on each chunk: on the polar chunk, rows that turn
+# hot within it, so that their chains start far below 2^-900, pass many rescales and fold (loading
+# their cotangents) during the walk
+ADJ_CHUNKS = {"equatorial": (NRING // (2 * HALF) - 1, [4096, 7000, 8000]),
+              "polar": (0, [0, 700, 1500])}
+
+
+@pytest.mark.parametrize("chunk", ["equatorial", "polar"])
+def test_large4_batched_adjoint_chunk(B, orc, inputs, chunk):
     alm, blms = inputs
-    rings = chunk_rings(NRING // (2 * HALF) - 1)
+    c, msel = ADJ_CHUNKS[chunk]
+    rings = chunk_rings(c)
     x = S.ring_cosines(NRING)[rings]
     shape = (2 * M + 1, L + 1, x.size)
     nC = 16 * int(np.prod(shape))
@@ -162,7 +173,7 @@ def test_large4_batched_adjoint_equatorial_chunk(B, orc, inputs):
     a_d = dev(alm)
     dets = [{"lmax": L, "mbmax": M, "cosbeta": x, "blm": dev(b),
              "C": torch.empty(shape, dtype=torch.complex128, device="cuda")} for b in blms]
-    say(f"large4 forward for the dot products: chunk of {x.size} rings")
+    say(f"large4 forward for the dot products: {chunk} chunk of {x.size} rings")
     plan = B.Plan(B.TC_OP_FWD, dets, L, a_d)
     plan.execute()
     torch.cuda.synchronize()
@@ -192,7 +203,6 @@ def test_large4_batched_adjoint_equatorial_chunk(B, orc, inputs):
         say(f"  detector {d}: <G,C> = {lhs[d]:.9e}  <b,beam_bar> = {rhs_b:.9e}")
         assert abs(lhs[d] - rhs_b) <= GATE * abs(lhs[d])
     # sampled rows of the summed sky gradient: every mb and ring of msky in msel
-    msel = [4096, 7000, 8000]
     nb = 2 * M + 1
     cols_mb = np.repeat(np.arange(-M, M + 1), len(msel)).astype(np.int32)
     cols_ms = np.tile(np.array(msel), nb).astype(np.int32)
