@@ -7,6 +7,7 @@ Gates (readings of the paper's silence on error metrics):
 * gradients: normwise over the whole sky gradient, per mb row for the beam gradient, <= 1e-11.
 Inputs are seeded synthetic rings, skies and beams (paper_1002_1050_amd.synthetic).
 """
+import contextlib
 import sys
 
 import numpy as np
@@ -169,14 +170,28 @@ def _sample_columns(L, M, n, seed):
     return mb.astype(np.int32), ms.astype(np.int32)
 
 
-@pytest.mark.parametrize("name,ncol", [("medium", 40), ("lmax4096", 16)])
-def test_fwd_full_size_sampled_columns(B, orc, name, ncol):
-    """Full-size launch (the benchmark's configuration); the oracle evaluates sampled columns
-    over every ring."""
+@contextlib.contextmanager
+def tile(B, op, t):
+    """Run with tile t = (R, TB, TR) for op (None: the built-in tile)."""
+    if t is not None:
+        B.set_tile_ex(op, *t)
+    try:
+        yield
+    finally:
+        B.set_tile_ex(op, 0, 0, 0)
+
+
+# the lmax 4096 launches at each tile the benchmark's autotuning picks on these boards
+@pytest.mark.parametrize("name,ncol,t", [("medium", 40, None), ("lmax4096", 16, (4, 64, 4)),
+                                         ("lmax4096", 16, (8, 64, 4))])
+def test_fwd_full_size_sampled_columns(B, orc, name, ncol, t):
+    """Full-size launch (the benchmark's configuration, at each tile it picks); the oracle
+    evaluates sampled columns over every ring."""
     w = S.WORKLOADS[name]
     x, alm, blm = w.xring(), w.alm(), w.blm()
-    say(f"totalconv_fwd {name} L={w.lmax} M={w.mbmax} nring={w.nring}")
-    C = run_fwd(B, w.lmax, w.mbmax, x, alm, blm)
+    say(f"totalconv_fwd {name} L={w.lmax} M={w.mbmax} nring={w.nring} tile {t or 'built-in'}")
+    with tile(B, B.TC_OP_FWD, t):
+        C = run_fwd(B, w.lmax, w.mbmax, x, alm, blm)
     mb, ms = _sample_columns(w.lmax, w.mbmax, ncol, 11)
     idx = torch.from_numpy(((mb + w.mbmax) * (w.lmax + 1) + ms).astype(np.int64)).to("cuda")
     got = C.reshape(-1, w.nring).index_select(0, idx).cpu().numpy()
@@ -280,23 +295,27 @@ def test_adj_dot_product_medium(B):
     assert abs(lhs - rhs_b) <= 1e-12 * abs(lhs)
 
 
-@pytest.mark.parametrize("name,msel", [("adjoint", [0, 7, 1500, 2048]), ("lmax4096", [0, 9, 3000, 4096])])
-def test_adj_large_sampled_sky_gradient(B, orc, name, msel):
+@pytest.mark.parametrize("name,msel,t", [("adjoint", [0, 7, 1500, 2048], None),
+                                         ("lmax4096", [0, 9, 3000, 4096], (8, 64, 4)),
+                                         ("lmax4096", [0, 9, 3000, 4096], (8, 32, 4))])
+def test_adj_large_sampled_sky_gradient(B, orc, name, msel, t):
     """Forward + adjoint at full size (lmax 2048 / 4096, the latter being the benchmark's
-    launch) with loss 0.5||C - C_target||^2; the oracle evaluates the sky gradient for sampled
-    msky (every mb and ring of those columns); the dot-product identities <G, C> = <sky_bar, a>
-    = <b, beam_bar> check the whole of both gradients."""
+    launch, at each adjoint tile its autotuning picks) with loss 0.5||C - C_target||^2; the oracle
+    evaluates the sky gradient for sampled msky (every mb and ring of those columns); the
+    dot-product identities <G, C> = <sky_bar, a> = <b, beam_bar> check the whole of both
+    gradients."""
     w = S.WORKLOADS[name]
     x, alm, blm = w.xring(), w.alm(), w.blm()
     target = S.sky_alm(w.lmax, w.target_seed)
-    say(f"adjoint workload L={w.lmax} M={w.mbmax} nring={w.nring}")
+    say(f"adjoint workload L={w.lmax} M={w.mbmax} nring={w.nring} adjoint tile {t or 'built-in'}")
     a_d, b_d = dev(alm), dev(blm)
     C = B.totalconv_fwd(w.lmax, w.mbmax, x, a_d, b_d)
     T = B.totalconv_fwd(w.lmax, w.mbmax, x, dev(target), b_d)
     G = C - T
     lhs = torch.vdot(G.flatten(), C.flatten()).item()
     del C, T
-    ga, gb = B.totalconv_adj(w.lmax, w.mbmax, x, a_d, b_d, G)
+    with tile(B, B.TC_OP_ADJ, t):
+        ga, gb = B.totalconv_adj(w.lmax, w.mbmax, x, a_d, b_d, G)
     rhs_a = torch.vdot(ga.flatten(), a_d.flatten()).item()
     rhs_b = torch.sum(torch.conj(b_d) * gb).item()
     say(f"  <G,C>={lhs:.9e}  <ga,a>={rhs_a:.9e}  <b,gb>={rhs_b:.9e}")
