@@ -75,24 +75,32 @@ def test_batched_forward_equals_plain_and_oracle(B, orc, R):
         blms.append(blm_h)
         dets.append({"lmax": L, "mbmax": M, "cosbeta": x, "blm": dev(blm_h),
                      "C": torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda")})
+    # plan and plain calls at one tile: which terms below the skip level a wavefront sums
+    # depends on which chains share it, so bitwise equality holds tile for tile
     B.set_tile(B.TC_OP_FWD, R)
-    say(f"batched forward plan, {len(dets)} detectors, R={R}")
-    plan = B.Plan(B.TC_OP_FWD, dets, LSKY, alm)
-    assert plan.tile == R
-    outs = []
-    for rep in range(3):
-        for d in dets:
-            d["C"].fill_(float("nan"))       # eager work between replays
-        plan.execute()
-        torch.cuda.synchronize()
-        outs.append([d["C"].cpu() for d in dets])
-    plan.close()
-    for rep in (1, 2):
-        for a, b in zip(outs[0], outs[rep]):
-            assert torch.equal(a, b), "graph replay differs"
+    try:
+        say(f"batched forward plan, {len(dets)} detectors, R={R}")
+        plan = B.Plan(B.TC_OP_FWD, dets, LSKY, alm)
+        assert plan.tile == R
+        outs = []
+        for rep in range(3):
+            for d in dets:
+                d["C"].fill_(float("nan"))       # eager work between replays
+            plan.execute()
+            torch.cuda.synchronize()
+            outs.append([d["C"].cpu() for d in dets])
+        plan.close()
+        for rep in (1, 2):
+            for a, b in zip(outs[0], outs[rep]):
+                assert torch.equal(a, b), "graph replay differs"
+        plains = []
+        for i, (L, M, x) in enumerate(DETS):
+            a_d = dev(truncate_sky(alm_h, LSKY, L))
+            plains.append(B.totalconv_fwd(L, M, x, a_d, dets[i]["blm"]).cpu())
+    finally:
+        B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     for i, (L, M, x) in enumerate(DETS):
-        a_d = dev(truncate_sky(alm_h, LSKY, L))
-        plain = B.totalconv_fwd(L, M, x, a_d, dets[i]["blm"]).cpu()
+        plain = plains[i]
         assert torch.equal(plain, outs[0][i]), f"detector {i}: batched != plain"
         ref = orc.totalconv_fwd(L, M, x, truncate_sky(alm_h, LSKY, L), blms[i])
         g = column_gate(outs[0][i].numpy(), ref)
@@ -158,10 +166,12 @@ def test_plan_rejects_bad_detectors(B):
         B.Plan(B.TC_OP_FWD, bad, 20, alm)
 
 
-def test_batched16_full_size_sampled(B, orc):
+@pytest.mark.parametrize("t", [None, (8, 64, 4)])
+def test_batched16_full_size_sampled(B, orc, t):
     """The sixteen-detector plan at full size (lmax 512..4096 x mbmax 4..14, 2 lmax rings each,
-    one sky at lmax 4096; the benchmark's batched workload): per detector, sampled columns of
-    the plan equal the plain call's bit for bit and match the oracle over every ring."""
+    one sky at lmax 4096; the benchmark's batched workload), at the built-in tile and at R 8 (the
+    plan tiles the benchmark's autotuning picks): per detector, sampled columns of the plan equal
+    the plain call's bit for bit and match the oracle over every ring."""
     w = S.WORKLOADS["batched16"]
     alm_h = S.sky_alm(w.lmax, w.sky_seed)
     alm = dev(alm_h)
@@ -172,7 +182,16 @@ def test_batched16_full_size_sampled(B, orc):
         dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": d.xring(), "blm": dev(blm_h),
                      "C": torch.empty((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128,
                                       device="cuda")})
-    say(f"batched16 plan at full size, {len(dets)} detectors")
+    say(f"batched16 plan at full size, {len(dets)} detectors, tile {t or 'built-in'}")
+    # plan and plain calls at one tile (bitwise equality holds tile for tile)
+    B.set_tile_ex(B.TC_OP_FWD, *(t or (0, 0, 0)))
+    try:
+        _batched16_check(B, orc, w, alm_h, alm, dets, blms)
+    finally:
+        B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
+
+
+def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
     plan = B.Plan(B.TC_OP_FWD, dets, w.lmax, alm)
     plan.execute()
     torch.cuda.synchronize()
