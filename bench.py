@@ -76,7 +76,9 @@ MEASURED_TRAFFIC = {
         "k_fwd": {"4,64,4": _bytes(2968655.5625 + 3722.5, 21857908.0625 + 0.0, 1048612.25),
                   "8,64,4": _bytes(1316486.6875 + 3718.5, 15350518.65625 + 0.0, 1048611.6875)},
         "k_adj": {"8,64,4": _bytes(5949830.5625, 15227927.84375, 1048612.25),
-                  "8,32,4": _bytes(5953789.8125, 15225733.03125, 1048611.6875)},
+                  "8,32,4": _bytes(5953789.8125, 15225733.03125, 1048611.6875),
+                  "4,64,4": _bytes(5907088.875, 30445755.46875, 1048611.0),
+                  "4,32,4": _bytes(5913510.4375, 30445764.78125, 1048611.6875)},
     },
 }
 
