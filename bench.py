@@ -407,8 +407,8 @@ def polarised_compare(w, x, alm, blm, reps, tune):
         tile = autotune.tune_plain(B.TC_OP_FWD_POL, w.lmax, w.mbmax, x, alms, blms, reps=1)
     B.set_tile_ex(B.TC_OP_FWD_POL, *tile)
     terms = 3 * w.terms()
-    res = {"workload": f"polarised forward, three (sky, beam) pairs, lmax={w.lmax}, mbmax={w.mbmax}, "
-                       f"{w.nring} rings", "terms": terms, "tile_R_TB": list(tile[:2])}
+    res = {"workload": f"polarised forward and adjoint, three (sky, beam) pairs, lmax={w.lmax}, "
+                       f"mbmax={w.mbmax}, {w.nring} rings", "terms": terms, "tile_R_TB": list(tile[:2])}
     for name, mode in (("separate", B.TC_POL_SEPARATE), ("summed", B.TC_POL_SUM)):
         outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, mode)   # warm-up
         del outs
@@ -427,6 +427,28 @@ def polarised_compare(w, x, alm, blm, reps, tune):
         log(f"  polarised {name}: kernel {kms:.1f} ms, {terms / (kms * 1e-3):.3e} terms/s")
         torch.cuda.empty_cache()
     B.set_tile_ex(B.TC_OP_FWD_POL, 0, 0, 0)
+    # the adjoint (totalconv_adj_pol, sky and beam gradients of every pair), the forward's outputs
+    # as cotangents: one per output (separate) or the first for the summed output; whole calls
+    # timed with events on the stream
+    outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, B.TC_POL_SEPARATE)
+    res["adjoint"] = {}
+    s = torch.cuda.current_stream(dev)
+    for name, mode, cbars in (("separate", B.TC_POL_SEPARATE, outs), ("summed", B.TC_POL_SUM, outs[:1])):
+        g = B.totalconv_adj_pol(w.lmax, w.mbmax, x, alms, blms, cbars, mode)   # warm-up
+        del g
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            g = B.totalconv_adj_pol(w.lmax, w.mbmax, x, alms, blms, cbars, mode)
+            del g
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res["adjoint"][name] = {"call_ms": round(ms, 3), "terms_per_s": terms / (ms * 1e-3)}
+        log(f"  polarised adjoint {name}: call {ms:.1f} ms, {terms / (ms * 1e-3):.3e} terms/s")
+    del outs
+    torch.cuda.empty_cache()
     return res
 
 
