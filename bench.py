@@ -112,7 +112,7 @@ def parse():
                    help="timed repetitions of the full-matrix generator at l = lmax on 16 rings (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
-    p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB' (skips its autotuning)")
+    p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB[,TR]' (skips its autotuning)")
     p.add_argument("--copy-calibration-gib", type=float, default=0.0,
                    help="first run one device-to-device copy of this many GiB (a reference kernel of known "
                         "traffic for hardware byte counters)")
@@ -493,8 +493,8 @@ def main():
     log("set-up done")
 
     def given(spec):
-        r, tb = (int(v) for v in spec.split(","))
-        return (r, tb, 4)
+        v = [int(u) for u in spec.split(",")]
+        return (v[0], v[1], v[2] if len(v) > 2 else 4)
 
     tf = given(args.tile_fwd) if args.tile_fwd else None
     ta = given(args.tile_adj) if args.tile_adj else None

@@ -238,8 +238,8 @@ int tc_set_tile(int op, int R);
 
 /*
  * Full tile selection: R chains per lane, TB values of l per LDS coefficient
- * block (32 or 64), TR steps per wave reduction of the adjoint's lane sums
- * (4).  0 keeps the built-in value of a parameter.  Same
+ * block (32 or 64) and TR (4, the only built value; kept so that tiles stay
+ * (R, TB, TR) triples).  0 keeps the built-in value of a parameter.  Same
  * scope and rules as tc_set_tile; TC_EINVAL for combinations that are not built.
  */
 int tc_set_tile_ex(int op, int R, int TB, int TR);

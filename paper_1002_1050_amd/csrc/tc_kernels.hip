@@ -30,7 +30,8 @@ namespace tc {
 namespace {
 
 // Tile parameters (template arguments): R chains per lane, NT lanes per workgroup,
-// TB values of l per coefficient block, TR steps per wave reduction (adjoint).
+// TB values of l per coefficient block; TR is kept in the tile triple (value 4) and no
+// longer shapes any kernel: the adjoint's row sums move every step.
 constexpr int TS = 8;         // steps between skip checks
 constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-900
 // A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
@@ -67,10 +68,11 @@ constexpr int fwd_min_waves() { return NC == 1 ? min_waves<R>() : (R >= 4 ? 2 : 
 template <int R>
 constexpr int rows_min_waves() { return R >= 8 ? 2 : 4; }
 
-// The adjoint's LDS (about 53 KB per workgroup with TB = 32, 62 KB with TB = 64)
-// caps residency at 3 or 2 workgroups (waves per SIMD) per CU.
+// The adjoint's LDS (about 37 KB per workgroup with TB = 32, 73 KB with TB = 64; mostly
+// the emitted row sums of two blocks) caps residency at 4 or 2 workgroups (waves per
+// SIMD) per CU.
 template <int R, int TB>
-constexpr int adj_min_waves() { return min_waves<R>() < (TB >= 64 ? 2 : 3) ? min_waves<R>() : (TB >= 64 ? 2 : 3); }
+constexpr int adj_min_waves() { return min_waves<R>() < (TB >= 64 ? 2 : 4) ? min_waves<R>() : (TB >= 64 ? 2 : 4); }
 
 // ------------------------------------------------------------- double-double
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
@@ -665,85 +667,82 @@ __global__ void __launch_bounds__(NT, W) k_fwd_queue(const FwdArgs* __restrict__
 // ================================================================== adjoint
 // Per column and l: u_l = sum_j d^l(beta_j) Cbar_j over the direct rings (U)
 // and sum_j d^l(beta_j) Cbar_{-mb,msky}(pi - beta_j) over the mirror rings (V).
-// Each lane sums its R chains in registers.  Every TR steps a wave reduces its
-// 64 lane sums of the 4 values per l through a wave-private LDS region (no
-// workgroup barrier); the waves' totals of a TB block are added in a fixed
-// order after the block's barrier and written out.  Deterministic throughout.
+//
+// Systolic row sums.  The 16 lanes of a row walk skewed: lane k (k = lane mod 16) is k
+// steps behind lane 0 of its row, so at the row's time t it is at l = l0 + t - k.  Each
+// lane carries four running sums (U re/im, V re/im).  Every step the sums move one lane
+// up the row (DPP row_shr:1; lane 0 of the row starts a fresh sum at 0) and the lane adds
+// d * Cbar of its R chains for its own l: a sum visits the 16 lanes of the row at the
+// same l and leaves lane 15 complete, 15 steps after it began, where it is written to
+// LDS.  After the TB block's barrier the four rows' and the waves' sums of each l are
+// added in a fixed order and written out.  No LDS round trip sits in the step loop and
+// nothing is reduced across lanes but the one shift per sum and step; the order of
+// every sum is fixed, so the result is deterministic.
 
-// Order the wave's LDS writes before its own later reads by other lanes.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+constexpr int ROW = 16;             // lanes per systolic row
+constexpr int SKEW = ROW - 1;       // steps lane 15 trails lane 0 of its row
 
-// Within a quad of lanes: the value of lane ^ 1 or lane ^ 2 (DPP quad permutes, no LDS).
-template <int OFF>
-__device__ __forceinline__ double quad_xor(double v)
+// The value of the lane one below in the same row of 16; lane 0 of a row gets 0.
+__device__ __forceinline__ double row_shift_up(double v)
 {
-    static_assert(OFF == 1 || OFF == 2, "quad permutes only");
-    constexpr int ctrl = OFF == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xF, 0xF, true);   // row_shr:1
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
-// Wave reduction buffer.  LDS serves 64-bit accesses 16 lanes at a time, so the
-// layout keeps every group of 16 lanes on 16 distinct bank pairs:
-//  - value v (step t, component c) owns a row of RED_ROW doubles (RED_ROW = 1 mod 16);
-//  - within a row the 64 lane sums sit in chunks of PER = 4 TR lanes, chunk k at
-//    k * red_chunk<TR>() (chunk stride = PER + 16 / GL), so a reading lane
-//    (value o, part k) starts at o * RED_ROW + k * chunk, and for the 16 lanes of a
-//    group (o mod 4, k) these starts are distinct modulo 16 doubles;
-//  - a writing lane n stores at v * RED_ROW + (n / PER) * chunk + n % PER: 16
-//    consecutive lanes write 16 consecutive doubles.
-constexpr int RED_ROW = 81;
+// Emitted row sums: slot (t - 16) mod 2 TB for the sum that leaves lane 15 at time t
+// (l offset t - 15), then (wave, row, component); slots are OUT_STRIDE doubles apart (one
+// more than the 4 NW 4 they hold, so that the reads of the block sum, one slot per lane,
+// spread over the LDS banks).
+template <int NT>
+constexpr int out_stride() { return (NT / 64) * 4 * 4 + 1; }
 
-template <int TR>
-constexpr int red_chunk() { return 4 * TR + 16 / (64 / (4 * TR)); }
-
-template <int NT, int TB, int TR>
+// The coefficient ring holds four blocks of TB l offsets plus a copy of its first TS
+// slots behind its end, so that the TS consecutive offsets of a step group never wrap.
+template <int NT, int TB>
 struct AdjShared {
-    double4 cf[2][TB];                          // {A, nB, F2, -}
-    double red[NT / 64][4 * TR][RED_ROW];       // per wave: value (step t, component c) x lane
-    double wsum[2][NT / 64][TB][4];             // per TB block parity, wave, step: reduced {P1r, P1i, P2r, P2i}
+    double2 cfa[4 * TB + TS];                     // {A, nB} per l offset, slot = offset mod 4 TB
+    double cff[4 * TB + TS];                      // F2 per l offset
+    double out[2 * TB * out_stride<NT>()];        // emitted row sums
 };
 
+template <int NT, int TB>
+constexpr size_t adj_lds_bytes() { return sizeof(AdjShared<NT, TB>); }
+
 template <int R, int NT, int TB, int TR>
-__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT, TB, TR>& sh_)
+__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT, TB>& sh_)
 {
-    static_assert(TS % TR == 0 && TR * 4 <= 64 && 64 % (TR * 4) == 0, "wave reduction split");
+    static_assert(TB % TS == 0 && TS % 2 == 0 && TB >= ROW, "step groups: pairs of steps, TS per check");
+    static_assert(TB * 4 <= NT, "block sum needs TB*4 threads");
     constexpr int NW = NT / 64;
-    constexpr int GL = 64 / (TR * 4);  // lanes per reduced value within a wave (a quad or less)
-    static_assert(GL <= 4, "in-quad combine");
-    constexpr int PER = 64 / GL;       // lane sums each reducing lane adds up
-    constexpr int CH = red_chunk<TR>();
-    static_assert(GL * CH <= RED_ROW, "reduction row");
-    static_assert(TB * 4 <= NT, "cross-wave sum needs TB*4 threads");
+    constexpr int CF_N = 4 * TB;            // coefficient ring: offset blocks kb-1, kb (read), kb+1 (staged)
+    constexpr int CF_MASK = CF_N - 1;
+    constexpr int OUT_MASK = 2 * TB - 1;    // emitted sums: windows kb (written) and kb-1 (summed)
+    constexpr int OS = out_stride<NT>();
+    static_assert((CF_N & CF_MASK) == 0 && (2 * TB & OUT_MASK) == 0 && (SKEW + 1) % TS == 0, "ring sizes");
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    const int kr = lane & (ROW - 1), row = lane >> 4;
     const int mb = a.col.mb[ci], ms = a.col.ms[ci];
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
+    const int n = L - l0 + 1;              // l values of a chain
     const SeedShape sh = seed_shape(mb, ms);
     const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
     const double2* Cbar = reinterpret_cast<const double2*>(a.Cbar);
     const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
+    const int s_base = tile * (NT * R) + tid * R;   // a wave: 64 R consecutive ring slots
 
     double x[R], d[R], dp[R], g1r[R], g1i[R], g2r[R], g2i[R];
-    int E[R], jd[R], jm[R];
+    int E[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int s = tile * (NT * R) + tid * R + r;   // a wave: 64 R consecutive ring pairs
-        jd[r] = -1; jm[r] = -1;
+        const int s = s_base + r;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
         g1r[r] = 0.0; g1i[r] = 0.0; g2r[r] = 0.0; g2i[r] = 0.0;
         if (s < a.nslot) {
-            jd[r] = a.slots[2 * s];
-            jm[r] = a.slots[2 * s + 1];
-            const int j = jd[r];
+            const int j = a.slots[2 * s];
             x[r] = a.ring.x[j];
             seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
         }
@@ -751,11 +750,13 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     // A scaled chain (E < 0, |d| < 2^-900) contributes nothing; its cotangent is
     // loaded when it folds into plain doubles.
     auto load_g = [&](int r) {
-        if (jd[r] >= 0 && E[r] == 0) {
-            const double2 v1 = Cbar[row_d + jd[r]];
+        const int s = s_base + r;
+        if (s < a.nslot && E[r] == 0) {
+            const int jd = a.slots[2 * s], jm = a.slots[2 * s + 1];
+            const double2 v1 = Cbar[row_d + jd];
             g1r[r] = v1.x; g1i[r] = v1.y;
-            if (jm[r] >= 0) {
-                const double2 v2 = Cbar[row_m + jm[r]];
+            if (jm >= 0) {
+                const double2 v2 = Cbar[row_m + jm];
                 g2r[r] = v2.x; g2i[r] = v2.y;
             }
         }
@@ -773,18 +774,63 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
 
-    const int st0 = stage_slot<NT, TB>(tid, 0);
-    if (st0 >= 0) {
-        double A, nB, F2;
-        recursion_coefs(l0 + st0, mb, ms, L, A, nB, F2);
-        sh_.cf[0][st0] = make_double4(A, nB, F2, 0.0);
-    }
+    auto stage = [&](int blk) {
+        const int st = stage_slot<NT, TB>(tid, blk);
+        if (st >= 0) {
+            double A, nB, F2;
+            recursion_coefs(l0 + blk * TB + st, mb, ms, L, A, nB, F2);
+            const int slot = (blk * TB + st) & CF_MASK;
+            sh_.cfa[slot] = make_double2(A, nB);
+            sh_.cff[slot] = F2;
+            if (slot < TS) {   // the copy behind the ring's end
+                sh_.cfa[CF_N + slot] = make_double2(A, nB);
+                sh_.cff[CF_N + slot] = F2;
+            }
+        }
+    };
+    // Lane 15 of each row stores the sums that leave it.  The sums alternate between two
+    // register sets step by step, so that the two sums a pair of steps completes are both
+    // still held after it and one store (a branch: only these lanes take it) serves two steps.
+    const bool exit_lane = kr == SKEW;
+    double* const outw = sh_.out + wave * 16 + row * 4;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   // set a: the sums after an odd step
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;   // set b: the sums after an even step
+    auto emit2 = [&](int t) {   // step t completed set b, step t + 1 set a; slots t - 16, t - 15
+        if (exit_lane) {
+            double* o = outw + ((t - SKEW - 1) & OUT_MASK) * OS;
+            o[0] = b0; o[1] = b1; o[2] = b2; o[3] = b3;
+            o = outw + ((t - SKEW) & OUT_MASK) * OS;
+            o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
+        }
+    };
+    auto shift_a_to_b = [&]() {
+        b0 = row_shift_up(a0); b1 = row_shift_up(a1); b2 = row_shift_up(a2); b3 = row_shift_up(a3);
+    };
+    auto shift_b_to_a = [&]() {
+        a0 = row_shift_up(b0); a1 = row_shift_up(b1); a2 = row_shift_up(b2); a3 = row_shift_up(b3);
+    };
+    // one step of the R chains of this lane: coefficients k, f2; the sums s0..s3 take d * Cbar
+    auto step = [&](const double2 k, const double f2, double& s0, double& s1, double& s2, double& s3) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s0 = fma(d[r], g1r[r], s0);
+            s1 = fma(d[r], g1i[r], s1);
+            s2 = fma(d[r], g2r[r], s2);
+            s3 = fma(d[r], g2i[r], s3);
+            const double u = fma(x[r], k.x, k.y);
+            const double dn = fma(-f2, dp[r], u * d[r]);
+            dp[r] = d[r];
+            d[r] = dn;
+        }
+    };
+
+    stage(0);
     __syncthreads();
     constexpr int RS_BLK = rs_block<TB>();   // steps between rescales of scaled chains
-    const int nblk = (L - l0) / TB + 1;
+    // lane 15 of a row finishes l = L at time n - 1 + SKEW
+    const int nblk = (n + SKEW + TB - 1) / TB;
     for (int kb = 0; kb < nblk; ++kb) {
-        const int buf = kb & 1;
-        const int lb = l0 + kb * TB;
+        const int buf_t = kb * TB;
         for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
             if (scaled) {
                 bool any = false;
@@ -799,92 +845,90 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 scaled = wave_any(any);
             }
             for (int s0 = s1; s0 < s1 + RS_BLK; s0 += TS) {
+                const int t0 = buf_t + s0;   // row time of the group's first step
+                // a lane that has not started yet holds its seed, so the test covers it
                 if (!acc_on)
                     acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
-                if (acc_on) {
-                    for (int h = 0; h < TS; h += TR) {
-                        // the group's coefficients are read before its first lane-sum store, so
-                        // the reads are in flight together instead of one round trip per step
-                        double4 kk[TR];
-#pragma unroll
-                        for (int t = 0; t < TR; ++t) kk[t] = sh_.cf[buf][s0 + h + t];
-                        __builtin_amdgcn_s_setprio(0);   // steps: normal issue priority
-#pragma unroll
-                        for (int t = 0; t < TR; ++t) {
-                            const double4 k = kk[t];
-                            double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
-#pragma unroll
-                            for (int r = 0; r < R; ++r) {
-                                p1r = fma(d[r], g1r[r], p1r);
-                                p1i = fma(d[r], g1i[r], p1i);
-                                p2r = fma(d[r], g2r[r], p2r);
-                                p2i = fma(d[r], g2i[r], p2i);
-                                const double u = fma(x[r], k.x, k.y);
-                                const double dn = fma(-k.z, dp[r], u * d[r]);
-                                dp[r] = d[r];
-                                d[r] = dn;
-                            }
-                            const int wpos = (lane / PER) * CH + lane % PER;
-                            sh_.red[wave][4 * t + 0][wpos] = p1r;
-                            sh_.red[wave][4 * t + 1][wpos] = p1i;
-                            sh_.red[wave][4 * t + 2][wpos] = p2r;
-                            sh_.red[wave][4 * t + 3][wpos] = p2i;
-                        }
-                        wave_lds_sync();
-                        // the reduction is a chain of dependent LDS reads, adds and DPP moves with
-                        // little work: raised priority lets it issue as soon as each operand is in,
-                        // ahead of the other wave's steps, up to the next group's coefficient reads
-                        __builtin_amdgcn_s_setprio(1);
-                        // lane -> value o = 4 t + c, part sub of GL; adds PER consecutive lane sums
-                        const int o = lane / GL, sub = lane - o * GL;
-                        const double* src = &sh_.red[wave][o][sub * CH];
-                        // all reads in flight at once, then a fixed binary tree
-                        double part[PER];
-#pragma unroll
-                        for (int i = 0; i < PER; ++i) part[i] = src[i];
-#pragma unroll
-                        for (int w2 = 1; w2 < PER; w2 <<= 1) {
-#pragma unroll
-                            for (int i = 0; i < PER; i += 2 * w2) part[i] += part[i + w2];
-                        }
-                        double v = part[0];
-                        if (GL >= 2) v += quad_xor<1>(v);
-                        if (GL >= 4) v += quad_xor<2>(v);
-                        if (sub == 0) sh_.wsum[buf][wave][s0 + h + (o >> 2)][o & 3] = v;
-                        wave_lds_sync();
-                    }
-                } else {
+                if (t0 < SKEW) {
+                    // start of the walk: lane k holds its chain (seed, 0) until time k and adds nothing
 #pragma unroll
                     for (int t = 0; t < TS; ++t) {
-                        const double4 k = sh_.cf[buf][s0 + t];
+                        const int tt = t0 + t;
+                        const bool live = tt >= kr;
+                        const int off = live ? tt - kr : 0;
+                        const double2 k = sh_.cfa[off & CF_MASK];
+                        const double f2 = sh_.cff[off & CF_MASK];
+                        if (t & 1) shift_b_to_a(); else shift_a_to_b();
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const double dd = (live && acc_on) ? d[r] : 0.0;
+                            if (t & 1) {
+                                a0 = fma(dd, g1r[r], a0); a1 = fma(dd, g1i[r], a1);
+                                a2 = fma(dd, g2r[r], a2); a3 = fma(dd, g2i[r], a3);
+                            } else {
+                                b0 = fma(dd, g1r[r], b0); b1 = fma(dd, g1i[r], b1);
+                                b2 = fma(dd, g2r[r], b2); b3 = fma(dd, g2i[r], b3);
+                            }
+                            const double u = fma(x[r], k.x, k.y);
+                            const double dn = fma(-f2, dp[r], u * d[r]);
+                            dp[r] = live ? d[r] : dp[r];
+                            d[r] = live ? dn : d[r];
+                        }
+                        if (t & 1) emit2(tt - 1);
+                    }
+                } else if (acc_on) {
+                    // pairs of steps; each pair's coefficients are read during the pair before
+                    const int cb = (t0 - kr) & CF_MASK;
+                    double2 kn0 = sh_.cfa[cb], kn1 = sh_.cfa[cb + 1];
+                    double fn0 = sh_.cff[cb], fn1 = sh_.cff[cb + 1];
+#pragma unroll
+                    for (int h = 0; h < TS; h += 2) {
+                        const double2 k0 = kn0, k1 = kn1;
+                        const double f0 = fn0, f1 = fn1;
+                        if (h + 2 < TS) {
+                            kn0 = sh_.cfa[cb + h + 2]; kn1 = sh_.cfa[cb + h + 3];
+                            fn0 = sh_.cff[cb + h + 2]; fn1 = sh_.cff[cb + h + 3];
+                        }
+                        shift_a_to_b();
+                        step(k0, f0, b0, b1, b2, b3);
+                        shift_b_to_a();
+                        step(k1, f1, a0, a1, a2, a3);
+                        emit2(t0 + h);
+                    }
+                } else {
+                    const int cb = (t0 - kr) & CF_MASK;
+#pragma unroll
+                    for (int t = 0; t < TS; ++t) {
+                        const double2 k = sh_.cfa[cb + t];
+                        const double f2 = sh_.cff[cb + t];
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const double u = fma(x[r], k.x, k.y);
-                            const double dn = fma(-k.z, dp[r], u * d[r]);
+                            const double dn = fma(-f2, dp[r], u * d[r]);
                             dp[r] = d[r];
                             d[r] = dn;
                         }
                     }
-                    if (lane < TS * 4) sh_.wsum[buf][wave][s0 + (lane >> 2)][lane & 3] = 0.0;
+                    // nothing is added yet: every sum of these steps is zero
+                    a0 = 0.0; a1 = 0.0; a2 = 0.0; a3 = 0.0; b0 = 0.0; b1 = 0.0; b2 = 0.0; b3 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < TS; t += 2) emit2(t0 + t);
                 }
             }
         }
-        const int st = stage_slot<NT, TB>(tid, kb + 1);
-        if (st >= 0 && kb + 1 < nblk) {
-            double A, nB, F2;
-            recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
-            sh_.cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
-        }
+        if (kb + 1 < nblk) stage(kb + 1);
         __syncthreads();
-        // totals of block kb: the waves' sums in a fixed order (the buffer of the
-        // other parity is being filled by the next block meanwhile)
+        // window kb: the sums of l offsets kb TB - 15 .. (kb+1) TB - 16, all emitted in this
+        // block; the waves and rows in a fixed order (the next block writes the other window)
         if (tid < TB * 4) {
-            const int t = tid >> 2, c = tid & 3;
-            double v = 0.0;
+            const int o = buf_t - SKEW + (tid >> 2), c = tid & 3;
+            if (o >= 0 && o < n) {
+                const double* src = sh_.out + ((o - 1) & OUT_MASK) * OS + c;
+                double v = 0.0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) v += sh_.wsum[buf][w][t][c];
-            const int l = lb + t;
-            if (l <= L) reinterpret_cast<double*>(c < 2 ? U : V)[2 * (urow + l) + (c & 1)] = v;
+                for (int w = 0; w < NW * 4; ++w) v += src[4 * w];
+                reinterpret_cast<double*>(c < 2 ? U : V)[2 * (urow + l0 + o) + (c & 1)] = v;
+            }
         }
     }
 }
@@ -892,7 +936,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
 template <int R, int NT, int TB, int TR>
 __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjArgs a)
 {
-    __shared__ AdjShared<NT, TB, TR> sh;
+    static_assert(adj_lds_bytes<NT, TB>() * adj_min_waves<R, TB>() <= 160 * 1024, "LDS per CU");
+    __shared__ AdjShared<NT, TB> sh;
     const int ci = blockIdx.x / a.ntile;
     adj_column<R, NT, TB, TR>(a, ci, blockIdx.x - ci * a.ntile, sh);
 }
@@ -901,7 +946,7 @@ template <int R, int NT, int TB, int TR>
 __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
                                                   int nitems, int* __restrict__ counter)
 {
-    __shared__ AdjShared<NT, TB, TR> sh;
+    __shared__ AdjShared<NT, TB> sh;
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -1027,9 +1072,8 @@ __global__ void __launch_bounds__(256) k_beam_symmetry(const double2* __restrict
 
 }  // namespace
 
-// Built tile variants.  Forward and adjoint: R in {2, 4, 8}, TB in {32, 64};
-// adjoint reductions every TR = 4 steps.  Polarised forward (op 3): R in {2, 4},
-// TB in {32, 64}.  Wigner: R in {1, 4}, TB = 32.
+// Built tile variants.  Forward and adjoint: R in {2, 4, 8}, TB in {32, 64}, TR = 4.
+// Polarised forward (op 3): R in {2, 4}, TB in {32, 64}.  Wigner: R in {1, 4}, TB = 32.
 bool tile_supported(int op, Tile t)
 {
     if (t.NT != 256) return false;
