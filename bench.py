@@ -194,19 +194,20 @@ def batched_compare(reps, tune):
     alm = torch.from_numpy(alm_h).to(dev)
     dets, plain = [], []
     for d in w.detectors:
-        x = d.xring()
+        beta = d.colatitudes()
+        x = B.rings_from_beta(beta)       # the library's rings, for the autotuner's cosine calls
         blm = torch.from_numpy(d.blm()).to(dev)
         C = torch.empty((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128, device=dev)
         a_d = torch.from_numpy(truncate_sky(S, alm_h, w.lmax, d.lmax)).to(dev)
         t = autotune.tune_plain(B.TC_OP_FWD, d.lmax, d.mbmax, x, a_d, blm, reps=1) if tune else (0, 0, 0)
-        dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": x, "blm": blm, "C": C})
-        plain.append((d, x, a_d, blm, C, t))
+        dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "beta": beta, "blm": blm, "C": C})
+        plain.append((d, beta, x, a_d, blm, C, t))
         log(f"  detector lmax={d.lmax} mbmax={d.mbmax} nring={d.nring} plain tile (R, TB, TR)={t}")
 
     def run_plain():
-        for d, x, a_d, blm, C, t in plain:
+        for d, beta, x, a_d, blm, C, t in plain:
             B.set_tile_ex(B.TC_OP_FWD, *t)
-            B.totalconv_fwd(d.lmax, d.mbmax, x, a_d, blm, out=C)
+            B.totalconv_fwd(d.lmax, d.mbmax, beta, a_d, blm, out=C)
         B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
 
     tp_ = (0, 0, 0)
@@ -274,30 +275,38 @@ def batched_adjoint_compare(w, dets, plain, alm, reps, tune):
     from paper_1002_1050_amd import autotune
     from paper_1002_1050_amd import synthetic as S
     dev = alm.device
-    adets = [{"lmax": d["lmax"], "mbmax": d["mbmax"], "cosbeta": d["cosbeta"], "blm": d["blm"],
+    adets = [{"lmax": d["lmax"], "mbmax": d["mbmax"], "beta": d["beta"], "blm": d["blm"],
               "Cbar": d["C"], "blm_bar": torch.empty_like(d["blm"])} for d in dets]
     alm_bar = torch.empty_like(alm)
     plain_bar = torch.zeros_like(alm)
     legs = []
-    for d, x, a_d, blm, C, _ in plain:
+    for d, beta, x, a_d, blm, C, _ in plain:
         # full-layout positions of the detector's truncated sky (m-major, l inner)
         ix = np.concatenate([np.arange(S.alm_index(w.lmax, m, m), S.alm_index(w.lmax, d.lmax, m) + 1)
                              for m in range(d.lmax + 1)])
         t = autotune.tune_plain(B.TC_OP_ADJ, d.lmax, d.mbmax, x, a_d, blm, C, reps=1) if tune else (0, 0, 0)
-        legs.append((d, x, a_d, blm, C, t, torch.from_numpy(ix).to(dev)))
+        legs.append((d, beta, a_d, blm, C, t, torch.from_numpy(ix).to(dev)))
         log(f"  adjoint detector lmax={d.lmax} mbmax={d.mbmax} plain tile (R, TB, TR)={t}")
 
     def run_plain():
         plain_bar.zero_()
-        for d, x, a_d, blm, C, t, ix in legs:
+        for d, beta, a_d, blm, C, t, ix in legs:
             B.set_tile_ex(B.TC_OP_ADJ, *t)
-            ab, _ = B.totalconv_adj(d.lmax, d.mbmax, x, a_d, blm, C)
+            ab, _ = B.totalconv_adj(d.lmax, d.mbmax, beta, a_d, blm, C)
             plain_bar.index_add_(0, ix, ab)
         B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
 
-    # the plan keeps its built-in tile: its partial sums grow as 1/R (about 50 GB at R 8 for these
-    # sixteen detectors), and a tuning trial at R 2 would need about 150 GB of them
+    # the plan is autotuned like the forward's: its partial sums (one U and one V row per column,
+    # about 25 GB for these sixteen detectors) do not depend on the tile
+    tp_ = (0, 0, 0)
+    tms = {}
+    if tune:
+        tp_, tms = autotune.tune_plan(B.TC_OP_ADJ, lambda: B.Plan(B.TC_OP_ADJ, adets, w.lmax, alm, alm_bar), reps=1,
+                                      key_extra="batched16")
+        log(f"  adjoint plan tile (R, TB, TR)={tp_} (trial ms {tms})")
+    B.set_tile_ex(B.TC_OP_ADJ, *tp_)
     plan = B.Plan(B.TC_OP_ADJ, adets, w.lmax, alm, alm_bar)
+    B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
     s = torch.cuda.current_stream(dev)
     run_plain()
     plan.execute()
@@ -328,7 +337,7 @@ def batched_adjoint_compare(w, dets, plain, alm, reps, tune):
         "speedup_median": float(np.median(ratios)),
         "speedup_min": float(np.min(ratios)),
         "speedup_max": float(np.max(ratios)),
-        "plan_tile": "built-in",
+        "plan_tile": list(tp_) if tune else "built-in",
         "plan_R": plan.tile,
         "reps": reps,
     }
@@ -370,14 +379,14 @@ def matrix_timing(w, reps, nring=16):
     from paper_1002_1050_amd import _binding as B
     from paper_1002_1050_amd import synthetic as S
     l = w.lmax
-    x = S.ring_cosines(2 * nring + 1)[1:nring + 1]
+    beta = S.ring_colatitudes(2 * nring + 1)[1:nring + 1]
     out = torch.empty((nring, 2 * l + 1, 2 * l + 1), dtype=torch.float64, device="cuda:0")
-    B.wigner_d_matrix(l, x, out=out)   # warm-up
+    B.wigner_d_matrix(l, beta, out=out)   # warm-up
     torch.cuda.synchronize()
     B.timing_enable(reps)
     t0 = time.perf_counter()
     for _ in range(reps):
-        B.wigner_d_matrix(l, x, out=out)
+        B.wigner_d_matrix(l, beta, out=out)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / reps
     kms = float(np.mean(B.timing_read(B.TC_OP_MATRIX, reps)))
@@ -391,7 +400,7 @@ def matrix_timing(w, reps, nring=16):
             "hbm_gb_per_s": 8 * n / (kms * 1e-3) / 1e9}
 
 
-def polarised_compare(w, x, alm, blm, reps, tune):
+def polarised_compare(w, beta, alm, blm, reps, tune):
     """Polarised forward on the same workload: temperature, gradient and curl pairs (three
     seeded skies, three beams) sharing one recursion, as three outputs and as their sum.
     Terms count each pair's (l, mb, msky, beta) terms."""
@@ -404,19 +413,19 @@ def polarised_compare(w, x, alm, blm, reps, tune):
     tile = B.get_tile_ex(B.TC_OP_FWD_POL, w.lmax)
     if tune:
         from paper_1002_1050_amd import autotune
-        tile = autotune.tune_plain(B.TC_OP_FWD_POL, w.lmax, w.mbmax, x, alms, blms, reps=1)
+        tile = autotune.tune_plain(B.TC_OP_FWD_POL, w.lmax, w.mbmax, B.rings_from_beta(beta), alms, blms, reps=1)
     B.set_tile_ex(B.TC_OP_FWD_POL, *tile)
     terms = 3 * w.terms()
     res = {"workload": f"polarised forward and adjoint, three (sky, beam) pairs, lmax={w.lmax}, "
                        f"mbmax={w.mbmax}, {w.nring} rings", "terms": terms, "tile_R_TB": list(tile[:2])}
     for name, mode in (("separate", B.TC_POL_SEPARATE), ("summed", B.TC_POL_SUM)):
-        outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, mode)   # warm-up
+        outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, beta, alms, blms, mode)   # warm-up
         del outs
         torch.cuda.synchronize()
         B.timing_enable(reps)
         t0 = time.perf_counter()
         for _ in range(reps):
-            outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, mode)
+            outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, beta, alms, blms, mode)
             del outs
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
@@ -430,17 +439,17 @@ def polarised_compare(w, x, alm, blm, reps, tune):
     # the adjoint (totalconv_adj_pol, sky and beam gradients of every pair), the forward's outputs
     # as cotangents: one per output (separate) or the first for the summed output; whole calls
     # timed with events on the stream
-    outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, x, alms, blms, B.TC_POL_SEPARATE)
+    outs = B.totalconv_fwd_pol(w.lmax, w.mbmax, beta, alms, blms, B.TC_POL_SEPARATE)
     res["adjoint"] = {}
     s = torch.cuda.current_stream(dev)
     for name, mode, cbars in (("separate", B.TC_POL_SEPARATE, outs), ("summed", B.TC_POL_SUM, outs[:1])):
-        g = B.totalconv_adj_pol(w.lmax, w.mbmax, x, alms, blms, cbars, mode)   # warm-up
+        g = B.totalconv_adj_pol(w.lmax, w.mbmax, beta, alms, blms, cbars, mode)   # warm-up
         del g
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         for _ in range(reps):
-            g = B.totalconv_adj_pol(w.lmax, w.mbmax, x, alms, blms, cbars, mode)
+            g = B.totalconv_adj_pol(w.lmax, w.mbmax, beta, alms, blms, cbars, mode)
             del g
         e1.record(s)
         torch.cuda.synchronize()
@@ -476,7 +485,8 @@ def main():
         raise SystemExit("batched workloads are timed by bench_batched")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    x = w.xring()
+    beta = w.colatitudes()
+    x = B.rings_from_beta(beta)           # the library's rings, for the autotuner's cosine calls
     alm_h, blm_h = w.alm(), w.blm()
     alm = torch.from_numpy(alm_h).to(dev)
     blm = torch.from_numpy(blm_h).to(dev)
@@ -485,8 +495,8 @@ def main():
 
     # untimed set-up: C, the target C_T from a second sky, cotangent G = C - C_T
     C = torch.empty((2 * w.mbmax + 1, w.lmax + 1, w.nring), dtype=torch.complex128, device=dev)
-    B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
-    T = B.totalconv_fwd(w.lmax, w.mbmax, x, torch.from_numpy(S.sky_alm(w.lmax, w.target_seed or 1050)).to(dev), blm)
+    B.totalconv_fwd(w.lmax, w.mbmax, beta, alm, blm, out=C)
+    T = B.totalconv_fwd(w.lmax, w.mbmax, beta, torch.from_numpy(S.sky_alm(w.lmax, w.target_seed or 1050)).to(dev), blm)
     G = C - T
     del T
     torch.cuda.synchronize()
@@ -513,9 +523,9 @@ def main():
     tiles = {"forward": list(tf), "adjoint": list(ta)}
 
     def step():
-        B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
+        B.totalconv_fwd(w.lmax, w.mbmax, beta, alm, blm, out=C)
         if not args.fwd_only:
-            B.totalconv_adj(w.lmax, w.mbmax, x, alm, blm, G)
+            B.totalconv_adj(w.lmax, w.mbmax, beta, alm, blm, G)
 
     for i in range(args.warmup):
         step()
@@ -530,10 +540,10 @@ def main():
     for i in range(args.steps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record(stream)
-        B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm, out=C)
+        B.totalconv_fwd(w.lmax, w.mbmax, beta, alm, blm, out=C)
         e[1].record(stream)
         if not args.fwd_only:
-            B.totalconv_adj(w.lmax, w.mbmax, x, alm, blm, G)
+            B.totalconv_adj(w.lmax, w.mbmax, beta, alm, blm, G)
         e[2].record(stream)
         ev.append(e)
     torch.cuda.synchronize()
@@ -629,7 +639,8 @@ def main():
             return Gc.index_select(0, idx).cpu().numpy()
 
         log(f"cpu baseline: oracle on a sample, about {args.cpu_seconds:.0f} s")
-        result["cpu_baseline"] = cpu_baseline(w, x, alm_h, blm_h, g_cols, args.cpu_seconds)
+        import oracle
+        result["cpu_baseline"] = cpu_baseline(w, oracle.ring_grid_x(beta), alm_h, blm_h, g_cols, args.cpu_seconds)
         del Gc
     B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
@@ -637,7 +648,7 @@ def main():
         del C
         torch.cuda.empty_cache()
         log("polarised forward")
-        result["polarised"] = side_leg("polarised forward", polarised_compare, w, x, alm, blm, args.pol_reps,
+        result["polarised"] = side_leg("polarised forward", polarised_compare, w, beta, alm, blm, args.pol_reps,
                                        not args.no_tune)
         C = None
     if args.batched_reps > 0:

@@ -7,10 +7,18 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - d^l_{m m'}(beta) = <l m| exp(-i beta J_y) |l m'>  (Sec. 2, eq. reducedwignerdef).
- * - A ring is given by x = cos(beta), a double in [-1, 1] (the per-ring cos(beta)
- *   of Sec. 4.2.2).  Rings j and nring-1-j form a mirror pair (beta, pi - beta)
- *   when x[nring-1-j] == -x[j] exactly; such pairs share one recursion
- *   (Sec. 4.2.3, appendix eq. pithetasym).  Any other ring is computed on its own.
+ * - Rings.  The problem is stated on colatitudes beta_j in [0, pi] (Sec. 4.1, the
+ *   beta grid of eqs. conviqt and convdef).  The library turns them into the ring
+ *   cosines it computes on, once per call (tc_rings_from_beta): x_j = cos(beta_j)
+ *   evaluated in long double and rounded once to double (the per-ring cos(beta) that
+ *   Sec. 4.2.2 precomputes; the poles are allowed), and for each j < k = nring-1-j
+ *   whose colatitudes add up to pi within 2^-48 (a grid symmetric about the equator,
+ *   rounded to doubles) the ring with the larger colatitude gets exactly -x of the
+ *   other.  Rings j and nring-1-j with x[nring-1-j] == -x[j] form a mirror pair
+ *   (beta, pi - beta) and share one recursion (Sec. 4.2.3, appendix eq.
+ *   pithetasym); any other ring is computed on its own.  Every entry point that
+ *   takes rings has a twin with the suffix _x that takes the cosines x directly
+ *   (doubles in [-1, 1]; same pairing rule on x).
  * - Complex arrays are interleaved FP64 pairs (re, im), 16-byte aligned.
  * - Sky ("alm"): s_{l,m} for 0 <= m <= l <= lmax, packed m-major,
  *   index(l, m) = m*(2*lmax+1-m)/2 + l; s_{l,-m} = (-1)^m conj(s_{l,m}) is implied
@@ -28,10 +36,12 @@
  *   of the current HIP device.  The caller owns all memory; the library never
  *   frees a caller buffer.
  * - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL for the
- *   default stream) and the call returns without waiting for it, except that
- *   the small host-computed tables are copied into the workspace on that stream
- *   before the call returns.  Buffers must stay valid until the stream has
- *   passed the call.
+ *   default stream) and the call returns without waiting for it.  The small
+ *   host-computed tables (rings, column list, seed normalisations) are copied into
+ *   the workspace on that stream; the library keeps their host images for the
+ *   calls of recent shapes and ring sets (at most 64, 1 GiB in all) in pinned
+ *   memory it allocates and frees itself, so that a repeated call only enqueues
+ *   that copy.  Buffers must stay valid until the stream has passed the call.
  * - Return value 0 on success, otherwise one of the negative TC_E* codes;
  *   tc_last_error() returns a message for the calling thread's last failure.
  *   Invalid arguments are rejected before any GPU work is enqueued.
@@ -81,11 +91,21 @@ int tc_abi_version(void);
 size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring);
 
 /*
- * As totalconv_workspace_bytes, for the given ring set (host, nring cosines):
- * exact when the rings form mirror pairs, which need fewer ring slots than the
- * worst case assumed above.  Returns 0 for invalid arguments.
+ * As totalconv_workspace_bytes, for the given ring set (host, nring colatitudes;
+ * _x: nring cosines): exact when the rings form mirror pairs, which need fewer
+ * ring slots than the worst case assumed above.  Returns 0 for invalid arguments.
  */
-size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* cosbeta);
+size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* beta);
+size_t totalconv_workspace_bytes_rings_x(int op, int lmax, int mbmax, int nring, const double* cosbeta);
+
+/*
+ * The ring cosines the library computes on for the colatitudes beta (host, nring
+ * doubles in [0, pi]): cosbeta[j] = cos(beta_j) in long double rounded once, with
+ * the mirror rule of the conventions above.  cosbeta: host output, nring doubles.
+ * TC_EINVAL for nring < 1, a NULL pointer or a colatitude outside [0, pi] (NaN
+ * included); nothing is written then.  Host only: touches no device.
+ */
+int tc_rings_from_beta(int nring, const double* beta, double* cosbeta);
 
 /*
  * Reduced Wigner elements by the l-recursion of Sec. 3.2 (seeds eqs. ini1..ini2
@@ -96,14 +116,17 @@ size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, c
  *   npair        number of (mb, msky) pairs, >= 1
  *   mb, msky     (host) npair integers each, |mb|, |msky| <= lmax
  *   nring        number of rings, >= 1
- *   cosbeta      (host) nring ring cosines in [-1, 1]
+ *   beta         (host) nring colatitudes in [0, pi] (_x: cosbeta, nring cosines in [-1, 1])
  *   d            out: [npair][lmax+1][nring] doubles, d[i][l][j] = d^l_{mb[i],msky[i]}(beta_j),
  *                0 for l < l0; values below the double range come out as 0 or subnormal
  *   workspace    at least totalconv_workspace_bytes(TC_OP_WIGNER, lmax, npair, nring) bytes
  */
 int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky,
-                   int nring, const double* cosbeta, double* d,
+                   int nring, const double* beta, double* d,
                    void* workspace, size_t ws_bytes, void* stream);
+int wigner_d_rings_x(int lmax, int npair, const int* mb, const int* msky,
+                     int nring, const double* cosbeta, double* d,
+                     void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * The full reduced Wigner matrix at one l (Sec. 3.1): d^l_{m m'}(beta_j) for
@@ -114,15 +137,17 @@ int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky,
  * other elements follow from the symmetries of the appendix.  This is the
  * recursion that the ratio form of Sec. 3.1 writes as ratios of neighbours.
  *   l            0 <= l <= TC_LMAX_LIMIT
- *   nring >= 1;  cosbeta (host) nring ring cosines in [-1, 1] (the poles included)
+ *   nring >= 1;  beta (host) nring colatitudes in [0, pi] (the poles included; _x: cosines)
  *   d            out: [nring][2l+1][2l+1] doubles, d[j][m+l][m'+l] = d^l_{m m'}(beta_j);
  *                values below the double range come out as 0 or subnormal
  *   workspace    at least wigner_d_matrix_workspace_bytes(l, nring) bytes
  * tc_set_tile(TC_OP_MATRIX, R) picks R in {1, 2} rows per lane (0: built-in).
  */
 size_t wigner_d_matrix_workspace_bytes(int l, int nring);
-int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d,
+int wigner_d_matrix(int l, int nring, const double* beta, double* d,
                     void* workspace, size_t ws_bytes, void* stream);
+int wigner_d_matrix_x(int l, int nring, const double* cosbeta, double* d,
+                      void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Total-convolution coefficients (Sec. 4.1, eq. convdef):
@@ -137,15 +162,18 @@ int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d,
  * the two rings' sums are formed from the sums over even and over odd l, which changes
  * only the rounding.
  *   lmax, mbmax  0 <= mbmax <= lmax <= TC_LMAX_LIMIT
- *   nring        >= 1;  cosbeta (host) nring ring cosines in [-1, 1]
+ *   nring        >= 1;  beta (host) nring colatitudes in [0, pi] (_x: cosbeta, cosines in [-1, 1])
  *   alm          sky, (lmax+1)(lmax+2)/2 complex
  *   blm          beam, (2*mbmax+1)*(lmax+1) complex
  *   C            out: (2*mbmax+1)*(lmax+1)*nring complex
  *   workspace    at least totalconv_workspace_bytes(TC_OP_FWD, lmax, mbmax, nring) bytes
  */
-int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta,
+int totalconv_fwd(int lmax, int mbmax, int nring, const double* beta,
                   const double* alm, const double* blm, double* C,
                   void* workspace, size_t ws_bytes, void* stream);
+int totalconv_fwd_x(int lmax, int mbmax, int nring, const double* cosbeta,
+                    const double* alm, const double* blm, double* C,
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of totalconv_fwd (not in the paper; the exact transpose of eq. convdef).
@@ -156,10 +184,14 @@ int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta,
  * may each be NULL; blm_bar entries with l < |mb| are written as 0.
  *   workspace    at least totalconv_workspace_bytes(TC_OP_ADJ, lmax, mbmax, nring) bytes
  */
-int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
+int totalconv_adj(int lmax, int mbmax, int nring, const double* beta,
                   const double* alm, const double* blm, const double* Cbar,
                   double* alm_bar, double* blm_bar,
                   void* workspace, size_t ws_bytes, void* stream);
+int totalconv_adj_x(int lmax, int mbmax, int nring, const double* cosbeta,
+                    const double* alm, const double* blm, const double* Cbar,
+                    double* alm_bar, double* blm_bar,
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Polarised total convolution (footnote of Sec. 4.1: eq. convdef evaluated for
@@ -178,9 +210,12 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta,
  * pairs it covers.  TC_EINVAL for npair outside [1, 3], an unknown mode or a
  * NULL pointer among the used entries.
  */
-int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* beta, int npair,
                       const double* const* alm, const double* const* blm, int mode,
                       double* const* C, void* workspace, size_t ws_bytes, void* stream);
+int totalconv_fwd_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+                        const double* const* alm, const double* const* blm, int mode,
+                        double* const* C, void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of totalconv_fwd_pol.  Cbar: (host) array of device pointers to the
@@ -192,10 +227,14 @@ int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int
  * TC_POL_SEPARATE mode the cotangents are reduced one after the other.
  *   workspace    at least totalconv_workspace_bytes(TC_OP_ADJ, lmax, mbmax, nring) bytes
  */
-int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* beta, int npair,
                       const double* const* alm, const double* const* blm, int mode,
                       const double* const* Cbar, double* const* alm_bar, double* const* blm_bar,
                       void* workspace, size_t ws_bytes, void* stream);
+int totalconv_adj_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, int npair,
+                        const double* const* alm, const double* const* blm, int mode,
+                        const double* const* Cbar, double* const* alm_bar, double* const* blm_bar,
+                        void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Data cube (Sec. 4.1, eq. conviqt): from the coefficients C of totalconv_fwd,
@@ -261,7 +300,9 @@ typedef struct tc_detector {
     int lmax;                /* 0 <= mbmax <= lmax <= lmax_sky                     */
     int mbmax;
     int nring;
-    const double* cosbeta;   /* (host) nring ring cosines, copied at plan creation  */
+    const double* beta;      /* (host) nring colatitudes in [0, pi], or NULL:      */
+    const double* cosbeta;   /* (host) nring ring cosines, used when beta is NULL;  */
+                             /* either is read at plan creation only                */
     const double* blm;       /* beam [2*mbmax+1][lmax+1] complex                    */
     double* C;               /* forward: out [2*mbmax+1][lmax+1][nring] complex     */
     const double* Cbar;      /* adjoint: in, layout of C                            */

@@ -56,6 +56,8 @@ def _load():
             lib.oracle_totalconv_fwd.argtypes = [I, I, I, P, P, P, I, P, P, I, P, ctypes.c_double, P, I]
             lib.oracle_totalconv_u.argtypes = [I, I, I, P, P, I, P, P, P, I]
             lib.oracle_ring_x.argtypes = [I, P, P]
+            lib.oracle_ring_grid_x.argtypes = [I, P, P]
+            lib.oracle_ring_grid_x.restype = ctypes.c_int
             lib.oracle_datacube.argtypes = [I, I, I, P, I, I, I, P, P, P, P, I]
             lib.oracle_datacube.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
@@ -83,6 +85,16 @@ def ring_x(beta) -> np.ndarray:
     beta = _c(beta, np.float64)
     x = np.empty_like(beta)
     _load().oracle_ring_x(beta.size, _ptr(beta), _ptr(x))
+    return x
+
+
+def ring_grid_x(beta) -> np.ndarray:
+    """Rings of a colatitude grid: ring_x of each colatitude, and for every pair j < k =
+    nring-1-j whose colatitudes add up to pi to within 2^-48 the ring with the larger colatitude
+    set to exactly minus the other's x (an exact mirror pair, Sec. 4.2.3)."""
+    beta = _c(beta, np.float64)
+    x = np.empty_like(beta)
+    _load().oracle_ring_grid_x(beta.size, _ptr(beta), _ptr(x))
     return x
 
 

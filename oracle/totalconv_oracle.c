@@ -422,6 +422,26 @@ int oracle_ring_x(int nring, const double* beta, double* x)
     return 0;
 }
 
+/* The rings of a colatitude grid: oracle_ring_x for each ring, then, for every pair of
+ * rings j < k = nring-1-j whose colatitudes add up to pi to within 2^-48 (a grid symmetric
+ * about the equator whose colatitudes were rounded to doubles), the ring with the larger
+ * colatitude takes exactly minus the other ring's x, so that the pair is an exact mirror
+ * pair (beta, pi - beta) of Sec. 4.2.3. */
+int oracle_ring_grid_x(int nring, const double* beta, double* x)
+{
+    const ld pi = 3.14159265358979323846264338327950288L;
+    const ld tol = 0x1p-48L;
+    oracle_ring_x(nring, beta, x);
+    for (int j = 0, k = nring - 1; j < k; ++j, --k) {
+        const ld gap = (ld)beta[j] + (ld)beta[k] - pi;
+        if (gap >= -tol && gap <= tol) {
+            if (beta[k] >= beta[j]) x[k] = -x[j];
+            else x[j] = -x[k];
+        }
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
     return omp_get_max_threads();

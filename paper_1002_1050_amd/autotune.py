@@ -100,12 +100,12 @@ def tune_plain(op, lmax, mbmax, cosbeta, alm, blm, Cbar=None, reps=2, use_cache=
             B.set_tile_ex(op, *t)
             try:
                 if op == B.TC_OP_FWD:
-                    times[t] = _time(lambda: B.totalconv_fwd(lmax, mbmax, cosbeta, alm, blm), reps)
+                    times[t] = _time(lambda: B.totalconv_fwd_x(lmax, mbmax, cosbeta, alm, blm), reps)
                 elif op == B.TC_OP_FWD_POL:   # alm, blm: lists of pairs; separate outputs
-                    times[t] = _time(lambda: B.totalconv_fwd_pol(lmax, mbmax, cosbeta, alm, blm), reps)
+                    times[t] = _time(lambda: B.totalconv_fwd_pol_x(lmax, mbmax, cosbeta, alm, blm), reps)
                 else:
                     B.workspace_cache.clear()
-                    times[t] = _time(lambda: B.totalconv_adj(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
+                    times[t] = _time(lambda: B.totalconv_adj_x(lmax, mbmax, cosbeta, alm, blm, Cbar), reps)
             except Exception as e:   # noqa: BLE001 - only a tile that does not fit in memory is skipped
                 if not _out_of_memory(e):
                     raise

@@ -3,7 +3,10 @@
 // workspace layout and the extern "C" entry points declared in totalconv.h.
 //
 // Tables (Sec. 4.2.2 of Prezeau & Reinecke, "compute just once"):
-//   per ring  j: x_j = cos(beta_j), ln cos(beta_j/2), ln sin(beta_j/2)
+//   rings      : from colatitudes beta_j, x_j = cos(beta_j) in long double rounded once, with
+//                rings j and nring-1-j made exact mirrors when beta_j + beta_{nring-1-j} is pi
+//                to within 2^-48 (see tc_rings_from_beta)
+//   per ring  j: x_j, ln cos(beta_j/2), ln sin(beta_j/2)
 //   per column : ln A = ln sqrt((2 l0)! / ((l0+m)! (l0-m)!)), the seed normalisation
 //                of Sec. 3.2 eq. logstart, with ln n! from lgammal
 //   ring slots : mirror pairs (j, nring-1-j) with x exactly negated, then the rest
@@ -16,6 +19,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -54,6 +59,34 @@ void split_dd(ld v, double& hi, double& lo)
 {
     hi = (double)v;
     lo = std::isinf(hi) ? 0.0 : (double)(v - (ld)hi);
+}
+
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+// Rings j and nring-1-j whose colatitudes add up to pi within this bound are taken as an
+// exact mirror pair (a grid symmetric about the equator, rounded to doubles).
+constexpr long double kMirrorTol = 0x1p-48L;
+
+// x_j = cos(beta_j) in long double rounded once to double; then for each j < k = nring-1-j
+// with |beta_j + beta_k - pi| <= 2^-48 the ring with the larger colatitude is set to the
+// exact negative of the other's x (the pi - beta symmetry of Sec. 4.2.3 then holds exactly).
+int rings_from_beta(int nring, const double* beta, std::vector<double>& x)
+{
+    if (nring < 1) return fail(TC_EINVAL, "nring must be >= 1 (got %d)", nring);
+    if (!beta) return fail(TC_EINVAL, "beta is NULL");
+    const double pi_d = (double)kPiL;   // the largest double not above pi
+    for (int j = 0; j < nring; ++j)
+        if (!(beta[j] >= 0.0 && beta[j] <= pi_d))
+            return fail(TC_EINVAL, "beta[%d] = %.17g is not a colatitude in [0, pi]", j, beta[j]);
+    x.resize(nring);
+    for (int j = 0; j < nring; ++j) x[j] = (double)cosl((long double)beta[j]);
+    for (int j = 0; j < nring / 2; ++j) {
+        const int k = nring - 1 - j;
+        if (fabsl((long double)beta[j] + (long double)beta[k] - kPiL) <= kMirrorTol) {
+            if (beta[j] <= beta[k]) x[k] = -x[j];
+            else x[j] = -x[k];
+        }
+    }
+    return TC_OK;
 }
 
 // ---------------------------------------------------------------- tile choice
@@ -156,9 +189,9 @@ Layout make_layout(int op, int lmax, int mbmax_or_npair, int nring, const double
     if (op == TC_OP_FWD || op == TC_OP_FWD_POL) {   // beam row signs, computed on the device
         L.sym = off; off = align_up(off + sizeof(int) * (size_t)(2 * mbmax_or_npair + 1));
     }
-    if (op == TC_OP_ADJ) {
+    if (op == TC_OP_ADJ) {   // one U and one V row per column, whatever the number of ring tiles
         L.P = (long long)(lmax + 1) * (lmax + 2) / 2;
-        const size_t ubytes = (size_t)16 * (size_t)L.ntile * (size_t)(2 * mbmax_or_npair + 1) * (size_t)L.P;
+        const size_t ubytes = (size_t)16 * (size_t)(2 * mbmax_or_npair + 1) * (size_t)L.P;
         L.U = off; off = align_up(off + ubytes);
         L.V = off; off = align_up(off + ubytes);
     }
@@ -276,6 +309,92 @@ int upload(void* ws, const std::vector<char>& img, void* stream)
     return rc ? hip_fail(rc, "table upload (hipMemcpyAsync)") : TC_OK;
 }
 
+// Host images of the per-call tables, kept in pinned memory for repeated calls with the same
+// (kind, sizes, tile, ring set, pair list) on the same device: a repeated call skips the long
+// double prep and the column sort, and its upload is an asynchronous copy from pinned memory.
+// Least recently used entries are dropped beyond kCacheEntries or kCacheBytes, after their last
+// upload has completed.  The images never change once built.
+struct TableImage {
+    std::vector<int> head;          // kind, device, lmax, mbmax / npair, nring, R, NT, bytes
+    std::vector<double> x;          // ring cosines
+    std::vector<int> pairs;         // (mb, msky) pairs of wigner_d_rings
+    void* pinned = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;      // recorded after the last upload from `pinned`
+};
+
+constexpr size_t kCacheEntries = 64;
+constexpr size_t kCacheBytes = (size_t)1 << 30;
+std::mutex g_cache_mu;
+std::list<TableImage> g_cache;      // front: most recently used
+
+void release_image(TableImage& e)
+{
+    // best effort at teardown and eviction: the copy that last read the image must be done
+    if (e.done) { (void)hipEventSynchronize(e.done); (void)hipEventDestroy(e.done); }
+    if (e.pinned) (void)hipHostFree(e.pinned);
+    e.done = nullptr;
+    e.pinned = nullptr;
+}
+
+bool same_key(const TableImage& e, const std::vector<int>& head, int nring, const double* x, int npair,
+              const int* mb, const int* ms)
+{
+    if (e.head != head || (int)e.x.size() != nring || (int)e.pairs.size() != 2 * npair) return false;
+    if (nring && std::memcmp(e.x.data(), x, sizeof(double) * nring)) return false;
+    for (int i = 0; i < npair; ++i)
+        if (e.pairs[2 * i] != mb[i] || e.pairs[2 * i + 1] != ms[i]) return false;
+    return true;
+}
+
+// Upload the table image for this call into the workspace, building it on a miss with
+// build(img).  kind: TC_OP_* of the layout.  For wigner_d_rings pass the pairs (else npair 0).
+template <class Build>
+int upload_tables(int kind, int lmax, int mbmax_or_npair, int nring, const double* x, int npair, const int* mb,
+                  const int* ms, const Layout& L, tc::Tile t, void* ws, void* stream, Build build)
+{
+    int dev = 0;
+    int rc = (int)hipGetDevice(&dev);
+    if (rc) return hip_fail(rc, "table upload: hipGetDevice");
+    const std::vector<int> head = {kind, dev, lmax, mbmax_or_npair, nring, t.R, t.NT, (int)L.tables_end};
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache.begin();
+    for (; it != g_cache.end(); ++it)
+        if (same_key(*it, head, nring, x, npair, mb, ms)) break;
+    if (it == g_cache.end()) {
+        std::vector<char> img(L.tables_end, 0);
+        build(img);
+        TableImage e;
+        e.head = head;
+        e.x.assign(x, x + nring);
+        for (int i = 0; i < npair; ++i) { e.pairs.push_back(mb[i]); e.pairs.push_back(ms[i]); }
+        e.bytes = img.size();
+        rc = (int)hipHostMalloc(&e.pinned, e.bytes, hipHostMallocDefault);
+        if (!rc) rc = (int)hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
+        if (rc) {   // no pinned memory: upload from the pageable image, uncached
+            (void)hipGetLastError();
+            release_image(e);
+            return upload(ws, img, stream);
+        }
+        std::memcpy(e.pinned, img.data(), e.bytes);
+        g_cache.push_front(std::move(e));
+        it = g_cache.begin();
+        size_t total = 0;
+        for (const TableImage& c : g_cache) total += c.bytes;
+        while (g_cache.size() > kCacheEntries || (g_cache.size() > 1 && total > kCacheBytes)) {
+            total -= g_cache.back().bytes;
+            release_image(g_cache.back());
+            g_cache.pop_back();
+        }
+    } else if (it != g_cache.begin()) {
+        g_cache.splice(g_cache.begin(), g_cache, it);
+        it = g_cache.begin();
+    }
+    rc = (int)hipMemcpyAsync(ws, it->pinned, it->bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (!rc) rc = (int)hipEventRecord(it->done, (hipStream_t)stream);
+    return rc ? hip_fail(rc, "table upload (hipMemcpyAsync)") : TC_OK;
+}
+
 tc::RingTables ring_ptrs(void* ws, const Layout& L, int nring)
 {
     const double* r = reinterpret_cast<const double*>(static_cast<char*>(ws) + L.ring);
@@ -314,11 +433,13 @@ int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int 
     const tc::Tile t = default_tile(op, lmax);
     const Layout L = make_layout(op, lmax, mbmax, nring, cosbeta, t);
     if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    std::vector<char> img(L.tables_end, 0);
-    build_rings(nring, cosbeta, img, L);
-    build_slots(nring, cosbeta, img, L);
-    build_columns(lmax, mbmax, img, L);
-    if ((rc = upload(workspace, img, stream))) return rc;
+    rc = upload_tables(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 0, nullptr, nullptr, L, t, workspace, stream,
+                       [&](std::vector<char>& img) {
+                           build_rings(nring, cosbeta, img, L);
+                           build_slots(nring, cosbeta, img, L);
+                           build_columns(lmax, mbmax, img, L);
+                       });
+    if (rc) return rc;
     tc::FwdArgs a{};
     a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
     a.sky_lmax = lmax;
@@ -366,11 +487,13 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
     const tc::Tile t = default_tile(TC_OP_ADJ, lmax);
     const Layout L = make_layout(TC_OP_ADJ, lmax, mbmax, nring, cosbeta, t);
     if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    std::vector<char> img(L.tables_end, 0);
-    build_rings(nring, cosbeta, img, L);
-    build_slots(nring, cosbeta, img, L);
-    build_columns(lmax, mbmax, img, L);
-    if ((rc = upload(workspace, img, stream))) return rc;
+    rc = upload_tables(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 0, nullptr, nullptr, L, t, workspace, stream,
+                       [&](std::vector<char>& img) {
+                           build_rings(nring, cosbeta, img, L);
+                           build_slots(nring, cosbeta, img, L);
+                           build_columns(lmax, mbmax, img, L);
+                       });
+    if (rc) return rc;
     tc::AdjArgs a{};
     a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
     a.skip_exp = 100;
@@ -387,11 +510,16 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
             need |= (alm_bar && alm_bar[p]) || (blm_bar && blm_bar[p]);
         if (!need) continue;
         a.Cbar = Cbar[k];
-        rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
+        // one launch per ring tile, in order: tile 0 writes each column's U and V, later tiles add
+        rc = timed_launch(TC_OP_ADJ, stream, [&] {
+            for (a.tile = 0; a.tile < L.ntile; ++a.tile)
+                if (int r = tc::launch_adj(a, t, stream)) return r;
+            return 0;
+        });
         if (rc) return hip_fail(rc, "totalconv_adj launch");
         for (int p = p0; p < p1; ++p) {
             tc::EpiArgs e{};
-            e.lmax = lmax; e.mbmax = mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax;
+            e.lmax = lmax; e.mbmax = mbmax; e.P = L.P; e.sky_lmax = lmax;
             e.U = a.U; e.V = a.V; e.alm = alm[p]; e.blm = blm[p];
             e.alm_bar = alm_bar ? alm_bar[p] : nullptr;
             e.blm_bar = blm_bar ? blm_bar[p] : nullptr;
@@ -420,7 +548,6 @@ MatrixLayout make_matrix_layout(int l, int nring)
 
 // ---------------------------------------------------------------- data cube
 
-constexpr long double kPiL = 3.14159265358979323846264338327950288L;
 constexpr size_t kCubeChunkBytes = (size_t)1 << 31;   // alpha sums held per ring chunk
 
 struct CubeLayout {
@@ -466,7 +593,7 @@ size_t wigner_d_matrix_workspace_bytes(int l, int nring)
     return make_matrix_layout(l, nring).total;
 }
 
-int wigner_d_matrix(int l, int nring, const double* cosbeta, double* d, void* workspace, size_t ws_bytes,
+int wigner_d_matrix_x(int l, int nring, const double* cosbeta, double* d, void* workspace, size_t ws_bytes,
                     void* stream)
 {
     g_error.clear();
@@ -635,7 +762,7 @@ int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR)
     return TC_OK;
 }
 
-int tc_abi_version(void) { return 1; }
+int tc_abi_version(void) { return 2; }
 
 int tc_timing_enable(int n)
 {
@@ -687,7 +814,7 @@ size_t totalconv_workspace_bytes(int op, int lmax, int mbmax, int nring)
     return make_layout(op, lmax, mbmax, nring, nullptr, default_tile(op, lmax)).total;
 }
 
-size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* cosbeta)
+size_t totalconv_workspace_bytes_rings_x(int op, int lmax, int mbmax, int nring, const double* cosbeta)
 {
     if (!cosbeta || totalconv_workspace_bytes(op, lmax, mbmax, nring) == 0) return 0;
     for (int j = 0; j < nring; ++j)
@@ -695,7 +822,7 @@ size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, c
     return make_layout(op, lmax, mbmax, nring, cosbeta, default_tile(op, lmax)).total;
 }
 
-int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nring, const double* cosbeta,
+int wigner_d_rings_x(int lmax, int npair, const int* mb, const int* msky, int nring, const double* cosbeta,
                    double* d, void* workspace, size_t ws_bytes, void* stream)
 {
     g_error.clear();
@@ -712,10 +839,12 @@ int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nrin
     const tc::Tile t = default_tile(TC_OP_WIGNER, lmax);
     const Layout L = make_layout(TC_OP_WIGNER, lmax, npair, nring, cosbeta, t);
     if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    std::vector<char> img(L.tables_end, 0);
-    build_rings(nring, cosbeta, img, L);
-    build_pairs(npair, mb, msky, img, L);
-    if ((rc = upload(workspace, img, stream))) return rc;
+    rc = upload_tables(TC_OP_WIGNER, lmax, npair, nring, cosbeta, npair, mb, msky, L, t, workspace, stream,
+                       [&](std::vector<char>& img) {
+                           build_rings(nring, cosbeta, img, L);
+                           build_pairs(npair, mb, msky, img, L);
+                       });
+    if (rc) return rc;
     tc::WignerArgs a{};
     a.lmax = lmax; a.npair = npair; a.nring = nring; a.ntile = L.ntile;
     a.ring = ring_ptrs(workspace, L, nring);
@@ -725,14 +854,14 @@ int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nrin
     return rc ? hip_fail(rc, "wigner_d_rings launch") : TC_OK;
 }
 
-int totalconv_fwd(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
+int totalconv_fwd_x(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
                   double* C, void* workspace, size_t ws_bytes, void* stream)
 {
     g_error.clear();
     return fwd_impl(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 1, &alm, &blm, 0, &C, workspace, ws_bytes, stream);
 }
 
-int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+int totalconv_fwd_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
                       const double* const* blm, int mode, double* const* C, void* workspace, size_t ws_bytes,
                       void* stream)
 {
@@ -744,7 +873,7 @@ int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* cosbeta, int
                     workspace, ws_bytes, stream);
 }
 
-int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
+int totalconv_adj_x(int lmax, int mbmax, int nring, const double* cosbeta, const double* alm, const double* blm,
                   const double* Cbar, double* alm_bar, double* blm_bar, void* workspace, size_t ws_bytes,
                   void* stream)
 {
@@ -753,7 +882,7 @@ int totalconv_adj(int lmax, int mbmax, int nring, const double* cosbeta, const d
                     stream);
 }
 
-int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
+int totalconv_adj_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
                       const double* const* blm, int mode, const double* const* Cbar, double* const* alm_bar,
                       double* const* blm_bar, void* workspace, size_t ws_bytes, void* stream)
 {
@@ -763,6 +892,91 @@ int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* cosbeta, int
     if (!alm || !blm || !Cbar) return fail(TC_EINVAL, "alm, blm or Cbar pointer array is NULL");
     return adj_impl(lmax, mbmax, nring, cosbeta, npair, alm, blm, mode == TC_POL_SUM ? 1 : 0, Cbar, alm_bar,
                     blm_bar, workspace, ws_bytes, stream);
+}
+
+// ----------------------------------------------------- entry points on colatitudes
+// Each forms the rings once (tc_rings_from_beta) and runs its *_x twin on them.
+
+int tc_rings_from_beta(int nring, const double* beta, double* cosbeta)
+{
+    g_error.clear();
+    if (!cosbeta) return fail(TC_EINVAL, "cosbeta (output) is NULL");
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    if (rc) return rc;
+    std::memcpy(cosbeta, x.data(), sizeof(double) * (size_t)nring);
+    return TC_OK;
+}
+
+size_t totalconv_workspace_bytes_rings(int op, int lmax, int mbmax, int nring, const double* beta)
+{
+    const std::string saved = g_error;
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    g_error = saved;
+    return rc ? 0 : totalconv_workspace_bytes_rings_x(op, lmax, mbmax, nring, x.data());
+}
+
+int wigner_d_rings(int lmax, int npair, const int* mb, const int* msky, int nring, const double* beta, double* d,
+                   void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc : wigner_d_rings_x(lmax, npair, mb, msky, nring, x.data(), d, workspace, ws_bytes, stream);
+}
+
+int wigner_d_matrix(int l, int nring, const double* beta, double* d, void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc : wigner_d_matrix_x(l, nring, x.data(), d, workspace, ws_bytes, stream);
+}
+
+int totalconv_fwd(int lmax, int mbmax, int nring, const double* beta, const double* alm, const double* blm, double* C,
+                  void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc : totalconv_fwd_x(lmax, mbmax, nring, x.data(), alm, blm, C, workspace, ws_bytes, stream);
+}
+
+int totalconv_fwd_pol(int lmax, int mbmax, int nring, const double* beta, int npair, const double* const* alm,
+                      const double* const* blm, int mode, double* const* C, void* workspace, size_t ws_bytes,
+                      void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc
+              : totalconv_fwd_pol_x(lmax, mbmax, nring, x.data(), npair, alm, blm, mode, C, workspace, ws_bytes,
+                                    stream);
+}
+
+int totalconv_adj(int lmax, int mbmax, int nring, const double* beta, const double* alm, const double* blm,
+                  const double* Cbar, double* alm_bar, double* blm_bar, void* workspace, size_t ws_bytes,
+                  void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc
+              : totalconv_adj_x(lmax, mbmax, nring, x.data(), alm, blm, Cbar, alm_bar, blm_bar, workspace, ws_bytes,
+                                stream);
+}
+
+int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* beta, int npair, const double* const* alm,
+                      const double* const* blm, int mode, const double* const* Cbar, double* const* alm_bar,
+                      double* const* blm_bar, void* workspace, size_t ws_bytes, void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    const int rc = rings_from_beta(nring, beta, x);
+    return rc ? rc
+              : totalconv_adj_pol_x(lmax, mbmax, nring, x.data(), npair, alm, blm, mode, Cbar, alm_bar, blm_bar,
+                                    workspace, ws_bytes, stream);
 }
 
 }  // extern "C"
@@ -804,16 +1018,26 @@ void destroy_plan(tc_plan_s* p)
     delete p;
 }
 
+// The rings of detector d: from its colatitudes (beta) or, when beta is NULL, its cosines.
+int detector_rings(int i, const tc_detector& d, std::vector<double>& x)
+{
+    int rc = TC_OK;
+    if (d.beta) {
+        rc = rings_from_beta(d.nring, d.beta, x);
+    } else {
+        rc = check_rings(d.nring, d.cosbeta);
+        if (!rc) x.assign(d.cosbeta, d.cosbeta + d.nring);
+    }
+    if (rc) g_error = "detector " + std::to_string(i) + ": " + g_error;
+    return rc;
+}
+
 int check_detector(int i, const tc_detector& d, int op, int lmax_sky)
 {
     if (d.lmax < 0 || d.lmax > lmax_sky)
         return fail(TC_EINVAL, "detector %d: lmax = %d outside [0, lmax_sky = %d]", i, d.lmax, lmax_sky);
     if (d.mbmax < 0 || d.mbmax > d.lmax)
         return fail(TC_EINVAL, "detector %d: mbmax = %d outside [0, lmax = %d]", i, d.mbmax, d.lmax);
-    if (int rc = check_rings(d.nring, d.cosbeta)) {
-        g_error = "detector " + std::to_string(i) + ": " + g_error;
-        return rc;
-    }
     if (!d.blm || !aligned16(d.blm)) return fail(TC_EINVAL, "detector %d: blm NULL or not 16-byte aligned", i);
     if (op == TC_OP_FWD && (!d.C || !aligned16(d.C)))
         return fail(TC_EINVAL, "detector %d: C NULL or not 16-byte aligned", i);
@@ -839,8 +1063,11 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     if (lmax_sky < 0 || lmax_sky > TC_LMAX_LIMIT) return fail(TC_EINVAL, "lmax_sky = %d out of range", lmax_sky);
     if (!alm || !aligned16(alm)) return fail(TC_EINVAL, "alm NULL or not 16-byte aligned");
     if (alm_bar && !aligned16(alm_bar)) return fail(TC_EINVAL, "alm_bar not 16-byte aligned");
-    for (int i = 0; i < ndet; ++i)
+    std::vector<std::vector<double>> xr(ndet);   // every detector's ring cosines
+    for (int i = 0; i < ndet; ++i) {
         if (int rc = check_detector(i, dets[i], op, lmax_sky)) return rc;
+        if (int rc = detector_rings(i, dets[i], xr[i])) return rc;
+    }
 
     tc_plan_s* p = new tc_plan_s;
     p->op = op;
@@ -854,7 +1081,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     size_t off = 0;
     long long nitems = 0;
     for (int i = 0; i < ndet; ++i) {
-        lay[i] = make_layout(op, dets[i].lmax, dets[i].mbmax, dets[i].nring, dets[i].cosbeta, p->tile);
+        lay[i] = make_layout(op, dets[i].lmax, dets[i].mbmax, dets[i].nring, xr[i].data(), p->tile);
         base[i] = off;
         off = align_up(off + lay[i].total);
         nitems += (long long)lay[i].ncol * lay[i].ntile;
@@ -890,8 +1117,8 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         const tc_detector& d = dets[i];
         const Layout& L = lay[i];
         std::vector<char> img(L.tables_end, 0);
-        build_rings(d.nring, d.cosbeta, img, L);
-        build_slots(d.nring, d.cosbeta, img, L);
+        build_rings(d.nring, xr[i].data(), img, L);
+        build_slots(d.nring, xr[i].data(), img, L);
         build_columns(d.lmax, d.mbmax, img, L);
         rc = (int)hipMemcpy(dm + base[i], img.data(), img.size(), hipMemcpyHostToDevice);
         if (rc) { destroy_plan(p); return hip_fail(rc, "plan: table upload"); }
@@ -929,11 +1156,20 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             a.P = L.P;
             tc::EpiArgs& e = ea[i];
             e = tc::EpiArgs{};
-            e.lmax = d.lmax; e.mbmax = d.mbmax; e.ntile = L.ntile; e.P = L.P; e.sky_lmax = lmax_sky;
+            e.lmax = d.lmax; e.mbmax = d.mbmax; e.P = L.P; e.sky_lmax = lmax_sky;
             e.U = a.U; e.V = a.V; e.alm = alm; e.blm = d.blm; e.alm_bar = nullptr; e.blm_bar = d.blm_bar;
         }
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    // forward: one queue, longest first.  Adjoint: one round per ring tile index, in order (tile 0
+    // writes each column's U and V, a later tile adds to them), each round longest first.
+    std::stable_sort(items.begin(), items.end(), [op](const Item& a, const Item& b) {
+        if (op == TC_OP_ADJ && a.tile != b.tile) return a.tile < b.tile;
+        return a.cost > b.cost;
+    });
+    std::vector<int> round_start(1, 0);   // item ranges of the rounds
+    for (size_t k = 1; k < items.size(); ++k)
+        if (op == TC_OP_ADJ && items[k].tile != items[k - 1].tile) round_start.push_back((int)k);
+    round_start.push_back((int)items.size());
     std::vector<int> it3(3 * items.size());
     for (size_t k = 0; k < items.size(); ++k) {
         it3[3 * k] = items[k].det;
@@ -987,8 +1223,14 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         rc = tc::launch_fwd_queue(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, counter,
                                   p->tile, p->rows, p->grid, cs);
     if (!rc && op == TC_OP_ADJ) {
-        rc = tc::launch_adj_queue(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items, p->nitems, counter,
-                                  p->tile, p->grid, cs);
+        for (size_t r = 0; r + 1 < round_start.size() && !rc; ++r) {
+            const int n = round_start[r + 1] - round_start[r];
+            if (r > 0) rc = tc::launch_reset_counter(counter, cs);
+            if (!rc)
+                rc = tc::launch_adj_queue(reinterpret_cast<const tc::AdjArgs*>(dm + args_off),
+                                          d_items + 3 * (size_t)round_start[r], n, counter, p->tile,
+                                          std::min(p->grid, n), cs);
+        }
         if (!rc && alm_bar)
             rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
                                           cs);

@@ -58,18 +58,19 @@ struct FwdArgs {
 
 struct AdjArgs {
     int lmax, mbmax, nring, nslot, ncol, ntile;
+    int tile;              // plain launch: the ring tile it walks (tile 0 writes U, V; later tiles add)
     int skip_exp;
     RingTables ring;
     const int* slots;
     ColumnTables col;
     const double* Cbar;    // layout of C
-    double* U;             // complex [ntile][2M+1][P] direct-ring partial sums u_l
-    double* V;             // complex [ntile][2M+1][P] mirror-ring partial sums (before the (-1)^(l-msky) sign)
+    double* U;             // complex [2M+1][P] direct-ring sums u_l (all ring tiles of a column)
+    double* V;             // complex [2M+1][P] mirror-ring sums (before the (-1)^(l-msky) sign)
     long long P;           // (L+1)(L+2)/2
 };
 
 struct EpiArgs {
-    int lmax, mbmax, ntile;
+    int lmax, mbmax;
     int sky_lmax;          // packing lmax of alm and alm_bar
     long long P;
     const double* U;

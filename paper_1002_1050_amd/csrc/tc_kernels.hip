@@ -770,8 +770,10 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     bool acc_on = (a.skip_exp <= 0);    // wave-uniform
     const double thr = hot_threshold(a.skip_exp);
 
-    double2* U = reinterpret_cast<double2*>(a.U) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
-    double2* V = reinterpret_cast<double2*>(a.V) + ((size_t)tile * (2 * a.mbmax + 1) + (mb + a.mbmax)) * (size_t)a.P;
+    // one U and one V row per column: ring tile 0 writes them, each later tile (a later launch,
+    // or a later round of the batched plan) adds to them
+    double2* U = reinterpret_cast<double2*>(a.U) + (size_t)(mb + a.mbmax) * (size_t)a.P;
+    double2* V = reinterpret_cast<double2*>(a.V) + (size_t)(mb + a.mbmax) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
 
     auto stage = [&](int blk) {
@@ -927,7 +929,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 double v = 0.0;
 #pragma unroll
                 for (int w = 0; w < NW * 4; ++w) v += src[4 * w];
-                reinterpret_cast<double*>(c < 2 ? U : V)[2 * (urow + l0 + o) + (c & 1)] = v;
+                double* dst = reinterpret_cast<double*>(c < 2 ? U : V) + 2 * (urow + l0 + o) + (c & 1);
+                *dst = (tile == 0) ? v : *dst + v;
             }
         }
     }
@@ -938,8 +941,7 @@ __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjA
 {
     static_assert(adj_lds_bytes<NT, TB>() * adj_min_waves<R, TB>() <= 160 * 1024, "LDS per CU");
     __shared__ AdjShared<NT, TB> sh;
-    const int ci = blockIdx.x / a.ntile;
-    adj_column<R, NT, TB, TR>(a, ci, blockIdx.x - ci * a.ntile, sh);
+    adj_column<R, NT, TB, TR>(a, blockIdx.x, a.tile, sh);
 }
 
 template <int R, int NT, int TB, int TR>
@@ -961,20 +963,13 @@ __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_queue(cons
 
 __global__ void k_reset_counter(int* counter) { counter[0] = 0; }
 
-// u(mb, ms, l) = sum_tiles U[mb] + (-1)^(l-ms) sum_tiles V[-mb], defined for l >= max(|mb|, ms)
+// u(mb, ms, l) = U[mb] + (-1)^(l-ms) V[-mb], defined for l >= max(|mb|, ms)
 __device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int l, size_t k)
 {
-    const double2* U = reinterpret_cast<const double2*>(e.U);
-    const double2* V = reinterpret_cast<const double2*>(e.V);
-    const size_t stride_t = (size_t)(2 * e.mbmax + 1) * (size_t)e.P;
-    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
-    for (int t = 0; t < e.ntile; ++t) {
-        const double2 a = U[t * stride_t + (size_t)(mb + e.mbmax) * e.P + k];
-        const double2 b = V[t * stride_t + (size_t)(-mb + e.mbmax) * e.P + k];
-        ur += a.x; ui += a.y; vr += b.x; vi += b.y;
-    }
+    const double2 a = reinterpret_cast<const double2*>(e.U)[(size_t)(mb + e.mbmax) * e.P + k];
+    const double2 b = reinterpret_cast<const double2*>(e.V)[(size_t)(-mb + e.mbmax) * e.P + k];
     const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
-    return make_double2(ur + sg * vr, ui + sg * vi);
+    return make_double2(a.x + sg * b.x, a.y + sg * b.y);
 }
 
 // Adds sum_mb b_{l,mb} u(mb, ms, l) of one detector to (ar, ai).
@@ -1138,7 +1133,7 @@ int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 
 int launch_adj(const AdjArgs& a, Tile t, void* stream)
 {
-    const int blocks = a.ncol * a.ntile;
+    const int blocks = a.ncol;   // ring tile a.tile of every column
 #define X(r, tb, tr) \
     if (t.R == r && t.TB == tb && t.TR == tr) return launch_grid(k_adj<r, 256, tb, tr>, a, blocks, 256, stream);
     TC_ADJ_VARIANTS(X)

@@ -139,6 +139,14 @@ def random_cbar(lmax: int, mbmax: int, nring: int, seed: int) -> np.ndarray:
     return (z[..., 0] + 1j * z[..., 1]) / math.sqrt(2.0)
 
 
+def random_cbar_row(lmax: int, mbmax: int, nring: int, seed: int, mb: int) -> np.ndarray:
+    """Row mb of a complex Gaussian cotangent for C, shape (lmax+1, nring), drawn from its own
+    stream PCG64([seed, mb + mbmax]) so that one row can be drawn without the others."""
+    rng = np.random.Generator(np.random.PCG64([seed, mb + mbmax]))
+    z = rng.standard_normal((lmax + 1, nring, 2))
+    return (z[..., 0] + 1j * z[..., 1]) / math.sqrt(2.0)
+
+
 def count_terms(lmax: int, mbmax: int, nring: int) -> int:
     """Number of (l, mb, msky, beta) terms: sum over chains of lmax - max(|mb|, msky) + 1."""
     t = 0
@@ -159,6 +167,9 @@ class Detector:
     def xring(self) -> np.ndarray:
         return ring_cosines(self.nring)
 
+    def colatitudes(self) -> np.ndarray:
+        return ring_colatitudes(self.nring)
+
     def blm(self) -> np.ndarray:
         return beam_blm(self.lmax, self.mbmax, self.fwhm_arcmin, self.ellipticity)
 
@@ -178,6 +189,9 @@ class Workload:
 
     def xring(self) -> np.ndarray:
         return ring_cosines(self.nring)
+
+    def colatitudes(self) -> np.ndarray:
+        return ring_colatitudes(self.nring)
 
     def alm(self) -> np.ndarray:
         return sky_alm(self.lmax, self.sky_seed, self.sky_taper)

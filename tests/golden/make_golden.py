@@ -3,7 +3,11 @@
 Calls only the oracle package: ``oracle.ring_x`` for the ring definition and
 ``oracle.mpref`` (mpmath, 40 significant digits) for reduced Wigner elements
 from the Jacobi-polynomial closed form, which is independent of the
-l-recursion.  Run from the repository root:  python tests/golden/make_golden.py
+l-recursion; and ``oracle.column_sums`` for one row of the adjoint's beam gradient
+(inputs from the seeded generators of ``paper_1002_1050_amd.synthetic``, which hold
+none of the method's arithmetic).  Run from the repository root:
+    python tests/golden/make_golden.py             (Jacobi points)
+    python tests/golden/make_golden.py beam_row    (beam-gradient row, minutes of CPU)
 """
 import json
 import os
@@ -40,7 +44,47 @@ def jacobi_points():
     return out
 
 
+def beam_gradient_row():
+    """One row of the beam gradient at the lmax 4096 workload (mbmax 14, 8192 rings, sky seed
+    1002): beam_bar_{l,mb} = sum_{msky <= l} s_{l,msky} conj(u_l(mb, msky)) with the oracle's
+    column sums u_l over every ring, for the seeded cotangent row synthetic.random_cbar_row
+    (seed 4096, mb 13; every other row zero).  About 7e10 oracle terms."""
+    from paper_1002_1050_amd import synthetic as S
+    L, M, nring, mb, seed = 4096, 14, 8192, 13, 4096
+    x = S.ring_cosines(nring)
+    alm = S.sky_alm(L, S.SKY_SEED)
+    G = S.random_cbar_row(L, M, nring, seed, mb)
+    ms = np.arange(L + 1, dtype=np.int32)
+    u = oracle.column_sums(L, M, x, G, (np.full(L + 1, mb, np.int32), ms))   # [msky][l][re, im]
+    ure, uim = u[..., 0], u[..., 1]
+    bre = np.zeros(L + 1, np.longdouble)
+    bim = np.zeros(L + 1, np.longdouble)
+    for m in range(L + 1):
+        start = S.alm_index(L, m, m)
+        s = alm[start:start + L + 1 - m]
+        sr, si = s.real.astype(np.longdouble), s.imag.astype(np.longdouble)
+        bre[m:] += sr * ure[m, m:] + si * uim[m, m:]      # s conj(u)
+        bim[m:] += si * ure[m, m:] - sr * uim[m, m:]
+    bre[:abs(mb)] = 0
+    bim[:abs(mb)] = 0
+    return {
+        "what": "beam-gradient row mb of the total-convolution adjoint (Sec. 4.1 eq. convdef, its exact "
+                "transpose) at lmax 4096, mbmax 14, 8192 rings synthetic.ring_cosines, sky "
+                "synthetic.sky_alm(4096, 1002), cotangent row synthetic.random_cbar_row(4096, 14, 8192, "
+                "4096, 13) and every other row zero; oracle column sums in x87 long double",
+        "lmax": L, "mbmax": M, "nring": nring, "mb": mb, "seed": seed,
+        "re": [float(v).hex() for v in bre.astype(np.float64)],
+        "im": [float(v).hex() for v in bim.astype(np.float64)],
+    }
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "beam_row":
+        doc = beam_gradient_row()
+        with open(os.path.join(HERE, "beam_gradient_row_lmax4096.json"), "w") as f:
+            json.dump(doc, f)
+        print("wrote beam-gradient row of", len(doc["re"]), "values")
+        return
     pts = jacobi_points()
     doc = {
         "what": "reduced Wigner elements d^l_{mb,msky}(beta_ring) from the Jacobi closed form "

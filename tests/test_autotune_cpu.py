@@ -34,7 +34,7 @@ def test_tile_out_of_memory_is_skipped(monkeypatch, fake):
             raise torch.cuda.OutOfMemoryError("out of memory")
         return None, None
 
-    monkeypatch.setattr(B, "totalconv_adj", adj)
+    monkeypatch.setattr(B, "totalconv_adj_x", adj)
     best = autotune.tune_plain(B.TC_OP_ADJ, 100, 4, np.zeros(8), None, None, None, reps=1, use_cache=False)
     assert best == (4, 64, 4)
 
@@ -45,14 +45,14 @@ def test_library_enomem_is_skipped_and_other_errors_propagate(monkeypatch, fake)
             raise B.TotalConvError("totalconv_fwd", B.TC_ENOMEM, "workspace")
         return None
 
-    monkeypatch.setattr(B, "totalconv_fwd", fwd_enomem)
+    monkeypatch.setattr(B, "totalconv_fwd_x", fwd_enomem)
     assert autotune.tune_plain(B.TC_OP_FWD, 100, 4, np.zeros(8), None, None, reps=1,
                                use_cache=False) == (4, 64, 4)
 
     def fwd_invalid(*a, **k):
         raise B.TotalConvError("totalconv_fwd", B.TC_EINVAL, "bad argument")
 
-    monkeypatch.setattr(B, "totalconv_fwd", fwd_invalid)
+    monkeypatch.setattr(B, "totalconv_fwd_x", fwd_invalid)
     with pytest.raises(B.TotalConvError):
         autotune.tune_plain(B.TC_OP_FWD, 100, 4, np.zeros(8), None, None, reps=1, use_cache=False)
 
@@ -61,7 +61,7 @@ def test_no_tile_fits(monkeypatch, fake):
     def adj(*a, **k):
         raise torch.cuda.OutOfMemoryError("out of memory")
 
-    monkeypatch.setattr(B, "totalconv_adj", adj)
+    monkeypatch.setattr(B, "totalconv_adj_x", adj)
     with pytest.raises(MemoryError):
         autotune.tune_plain(B.TC_OP_ADJ, 100, 4, np.zeros(8), None, None, None, reps=1, use_cache=False)
     assert fake["t"] == (0, 0, 0)                  # the built-in tile is restored

@@ -96,7 +96,7 @@ def test_batched_forward_equals_plain_and_oracle(B, orc, R):
         plains = []
         for i, (L, M, x) in enumerate(DETS):
             a_d = dev(truncate_sky(alm_h, LSKY, L))
-            plains.append(B.totalconv_fwd(L, M, x, a_d, dets[i]["blm"]).cpu())
+            plains.append(B.totalconv_fwd_x(L, M, x, a_d, dets[i]["blm"]).cpu())
     finally:
         B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     for i, (L, M, x) in enumerate(DETS):
@@ -140,7 +140,7 @@ def test_batched_adjoint_equals_plain_and_oracle(B, orc):
     ref_sum = np.zeros_like(alm_h)
     for i, (L, M, x) in enumerate(DETS):
         a_t = truncate_sky(alm_h, LSKY, L)
-        ga, gb = B.totalconv_adj(L, M, x, dev(a_t), dets[i]["blm"], dets[i]["Cbar"])
+        ga, gb = B.totalconv_adj_x(L, M, x, dev(a_t), dets[i]["blm"], dets[i]["Cbar"])
         assert torch.equal(gb.cpu(), res[0][1][i]), f"detector {i}: beam gradient batched != plain"
         sky_sum += pad_sky(ga.cpu().numpy(), L, LSKY)
         ra, rb = orc.totalconv_adj(L, M, x, a_t, blms[i], Gs[i])
@@ -209,7 +209,7 @@ def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
         idx = torch.from_numpy(((mb + M) * (L + 1) + ms).astype(np.int64)).to("cuda")
         got = det["C"].reshape(-1, x.size).index_select(0, idx).cpu()
         a_t = truncate_sky(alm_h, w.lmax, L)
-        plain = B.totalconv_fwd(L, M, x, dev(a_t), det["blm"])
+        plain = B.totalconv_fwd_x(L, M, x, dev(a_t), det["blm"])
         same = torch.equal(plain.reshape(-1, x.size).index_select(0, idx).cpu(), got)
         del plain
         det["C"] = None
@@ -245,7 +245,7 @@ def test_plan_follows_beams_changed_between_executions(B, first):
             plan.execute()
             torch.cuda.synchronize()
             for d in dets:
-                plain = B.totalconv_fwd(L, M, x, alm, d["blm"])
+                plain = B.totalconv_fwd_x(L, M, x, alm, d["blm"])
                 assert torch.equal(plain, d["C"]), "plan result differs from the plain call"
     finally:
         plan.close()

@@ -81,7 +81,7 @@ def test_cube_end_to_end_from_the_forward(B, orc):
     alm = S.sky_alm(L, 21)
     blm = S.beam_blm(L, M, 30.0, 0.2)
     say("forward + datacube end to end")
-    Cg = B.totalconv_fwd(L, M, x, torch.from_numpy(alm).cuda(), torch.from_numpy(blm).cuda())
+    Cg = B.totalconv_fwd_x(L, M, x, torch.from_numpy(alm).cuda(), torch.from_numpy(blm).cuda())
     got = B.totalconv_datacube(L, M, Cg, Na, Ng).cpu().numpy()
     ref = orc.datacube(L, M, orc.totalconv_fwd(L, M, x, alm, blm), Na, Ng)
     gate = ring_gate(got, ref)
@@ -123,7 +123,7 @@ def test_cube_full_size_from_the_forward_sampled(B, orc):
     w = S.WORKLOADS["lmax4096"]
     L, M, x = w.lmax, w.mbmax, w.xring()
     Na, Ng = 2 * M + 1, 2 * L
-    C = B.totalconv_fwd(L, M, x, torch.from_numpy(w.alm()).cuda(), torch.from_numpy(w.blm()).cuda())
+    C = B.totalconv_fwd_x(L, M, x, torch.from_numpy(w.alm()).cuda(), torch.from_numpy(w.blm()).cuda())
     say(f"datacube full size L={L} M={M} nring={x.size} nalpha={Na} ngamma={Ng}")
     B.timing_enable(64)
     cube = B.totalconv_datacube(L, M, C, Na, Ng)

@@ -4,8 +4,8 @@
 The rings are processed in chunks of 4096 (2048 mirror pairs, (j, 16383 - j)); C of one chunk
 is 17.7 GB per detector.  Each test runs a batched plan (one persistent launch over the four
 detectors) on one full chunk:
-* forward, polar chunk: sampled columns, covering every mb and every msky decile, against the
-  oracle over all 4096 rings (per-column gate 1e-11, widened by the epsilon skip's own bound
+* forward, on the polar and on the equatorial chunk: sampled columns, covering every mb and
+  every msky decile, against the oracle over all 4096 rings (per-column gate 1e-11, widened by the epsilon skip's own bound
   for columns that are cold on every ring of the chunk), and the plain call bitwise equal to
   the plan on detector 0;
 * adjoint, on the equatorial and on the polar chunk, with a seeded Gaussian cotangent: sampled
@@ -117,16 +117,22 @@ def sampled_columns(d, seed=8192):
     return mb, ms
 
 
-def test_large4_batched_forward_polar_chunk(B, orc, inputs):
+# forward chunks: the polar one (chains start far below 2^-900 for most msky) and the one next to
+# the equator (every column hot, the mirror pairs closest to pi/2)
+FWD_CHUNKS = {"polar": 0, "equatorial": NRING // (2 * HALF) - 1}
+
+
+@pytest.mark.parametrize("chunk", ["polar", "equatorial"])
+def test_large4_batched_forward_chunk(B, orc, inputs, chunk):
     alm, blms = inputs
-    rings = chunk_rings(0)
+    rings = chunk_rings(FWD_CHUNKS[chunk])
     x = S.ring_cosines(NRING)[rings]
     shape = (2 * M + 1, L + 1, x.size)
     need_memory(5 * 16 * int(np.prod(shape)) + 2 * 10**9)
     a_d = dev(alm)
     dets = [{"lmax": L, "mbmax": M, "cosbeta": x, "blm": dev(b),
              "C": torch.empty(shape, dtype=torch.complex128, device="cuda")} for b in blms]
-    say(f"large4 forward plan: {len(dets)} detectors, lmax {L}, mbmax {M}, chunk of {x.size} rings")
+    say(f"large4 forward plan: {len(dets)} detectors, lmax {L}, mbmax {M}, {chunk} chunk of {x.size} rings")
     plan = B.Plan(B.TC_OP_FWD, dets, L, a_d)
     plan.execute()
     torch.cuda.synchronize()
@@ -138,7 +144,7 @@ def test_large4_batched_forward_polar_chunk(B, orc, inputs):
         got = det["C"].reshape(-1, x.size).index_select(0, idx).cpu().numpy()
         if d == 0:
             say("  plain call, detector 0")
-            plain = B.totalconv_fwd(L, M, x, a_d, det["blm"])
+            plain = B.totalconv_fwd_x(L, M, x, a_d, det["blm"])
             same = torch.equal(plain.reshape(-1, x.size).index_select(0, idx).cpu(), torch.from_numpy(got))
             del plain
             assert same, "plain call differs from the batched plan"

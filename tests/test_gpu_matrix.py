@@ -42,7 +42,7 @@ def all_pairs(l):
 @pytest.mark.parametrize("l", [0, 1, 2, 7, 40, 300])
 def test_matrix_small_l_every_element(B, orc, l):
     say(f"wigner_d_matrix l={l} nring={RINGS.size}")
-    got = B.wigner_d_matrix(l, RINGS).cpu().numpy()
+    got = B.wigner_d_matrix_x(l, RINGS).cpu().numpy()
     m, mp = all_pairs(l)
     ref = orc.wigner_d(l, m, mp, RINGS)[:, l, :]                   # [pair][ring]
     ref = ref.T.reshape(RINGS.size, 2 * l + 1, 2 * l + 1)
@@ -55,7 +55,7 @@ def test_matrix_small_l_every_element(B, orc, l):
 def test_matrix_large_l_sampled_and_orthogonal(B, orc, l, gate):
     x = RINGS[[2, 3, 5, 6, 7]]
     say(f"wigner_d_matrix l={l} nring={x.size}")
-    got = B.wigner_d_matrix(l, x)
+    got = B.wigner_d_matrix_x(l, x)
     rng = np.random.Generator(np.random.PCG64(l))
     m = np.concatenate([rng.integers(-l, l + 1, 400), np.full(40, l), np.full(40, 0), np.arange(-20, 20)])
     mp = np.concatenate([rng.integers(-l, l + 1, 400), rng.integers(-l, l + 1, 40), rng.integers(-l, l + 1, 40),
@@ -76,9 +76,9 @@ def test_matrix_tiles_agree(B):
     l = 1500
     x = RINGS[2:7]
     B.set_tile(B.TC_OP_MATRIX, 1)
-    a = B.wigner_d_matrix(l, x)
+    a = B.wigner_d_matrix_x(l, x)
     B.set_tile(B.TC_OP_MATRIX, 2)
-    b = B.wigner_d_matrix(l, x)
+    b = B.wigner_d_matrix_x(l, x)
     B.set_tile(B.TC_OP_MATRIX, 0)
     assert torch.equal(a, b)
 
@@ -89,7 +89,7 @@ def test_matrix_benchmark_launch_sampled(B, orc):
     l, nring = 4096, 16
     x = S.ring_cosines(2 * nring + 1)[1:nring + 1]
     say(f"wigner_d_matrix l={l} nring={nring} (benchmark rings)")
-    got = B.wigner_d_matrix(l, x)
+    got = B.wigner_d_matrix_x(l, x)
     rng = np.random.Generator(np.random.PCG64(16 * l))
     m = np.concatenate([rng.integers(-l, l + 1, 300), [l, -l, 0, l, -l], np.arange(l - 70, l + 1)])
     mp = np.concatenate([rng.integers(-l, l + 1, 300), [l, -l, 0, -l, l], rng.integers(-l, l + 1, 71)])

@@ -60,7 +60,7 @@ def test_wigner_small_all_cases(B, orc):
     mb = [p[0] for p in pairs]
     ms = [p[1] for p in pairs]
     say(f"wigner_d_rings L={L} npair={len(pairs)} nring={x.size}")
-    got = B.wigner_d_rings(L, mb, ms, x).cpu().numpy()
+    got = B.wigner_d_rings_x(L, mb, ms, x).cpu().numpy()
     ref = orc.wigner_d(L, mb, ms, x)
     err = np.abs(got - ref).max()
     say(f"  max abs err {err:.3e}")
@@ -76,7 +76,7 @@ def test_wigner_large_l_sampled_rings(B, orc):
     mb = [p[0] for p in pairs]
     ms = [p[1] for p in pairs]
     say(f"wigner_d_rings L={L} npair={len(pairs)} nring={x.size}")
-    got = B.wigner_d_rings(L, mb, ms, x).cpu().numpy()
+    got = B.wigner_d_rings_x(L, mb, ms, x).cpu().numpy()
     ref = orc.wigner_d(L, mb, ms, x)
     err = np.abs(got - ref).max()
     say(f"  max abs err {err:.3e}")
@@ -91,7 +91,7 @@ def test_wigner_tiny_values_relative(B, orc):
     x = S.ring_cosines(4000)[[500, 550, 600, 620, 650, 700, 3300, 3350, 3400, 3450, 3500]]
     pairs = [(3, 800), (0, 1000), (-3, 800), (2, 1000)]
     say(f"wigner_d_rings tiny seeds L={L}")
-    got = B.wigner_d_rings(L, [p[0] for p in pairs], [p[1] for p in pairs], x).cpu().numpy()
+    got = B.wigner_d_rings_x(L, [p[0] for p in pairs], [p[1] for p in pairs], x).cpu().numpy()
     ref = orc.wigner_d(L, [p[0] for p in pairs], [p[1] for p in pairs], x)
     mant, ex = orc.wigner_d(L, [p[0] for p in pairs], [p[1] for p in pairs], x, split=True)
     l0 = np.array([max(abs(a), abs(b)) for a, b in pairs])
@@ -106,7 +106,7 @@ def test_wigner_tiny_values_relative(B, orc):
 # ------------------------------------------------------------------------ forward
 
 def run_fwd(B, L, M, x, alm, blm):
-    return B.totalconv_fwd(L, M, x, dev(alm), dev(blm))
+    return B.totalconv_fwd_x(L, M, x, dev(alm), dev(blm))
 
 
 def test_fwd_small_workload_full(B, orc):
@@ -225,7 +225,7 @@ def test_fwd_beam_rows_equal_up_to_sign(B, orc):
         kind = mb % 3
         blm[M - mb] = blm[M + mb] if kind == 0 else (-blm[M + mb] if kind == 1 else row(mb))
     say(f"totalconv_fwd rows +1 / -1 / general, L={L} M={M} nring={nring}")
-    got = B.totalconv_fwd(L, M, x, dev(alm), dev(blm)).cpu().numpy()
+    got = B.totalconv_fwd_x(L, M, x, dev(alm), dev(blm)).cpu().numpy()
     ref = orc.totalconv_fwd(L, M, x, alm, blm)
     g = column_gate(got, ref)
     say(f"  column gate {g:.3e}")
@@ -236,8 +236,8 @@ def test_fwd_deterministic(B):
     w = S.WORKLOADS["small"]
     x, alm, blm = w.xring(), dev(w.alm()), dev(w.blm())
     say("totalconv_fwd determinism")
-    a = B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm).cpu()
-    b = B.totalconv_fwd(w.lmax, w.mbmax, x, alm, blm).cpu()
+    a = B.totalconv_fwd_x(w.lmax, w.mbmax, x, alm, blm).cpu()
+    b = B.totalconv_fwd_x(w.lmax, w.mbmax, x, alm, blm).cpu()
     assert torch.equal(a, b)
 
 
@@ -248,9 +248,9 @@ def test_fwd_rejects_bad_input(B):
     bad = x.copy()
     bad[2] = 2.0
     with pytest.raises(B.TotalConvError, match="cosbeta"):
-        B.totalconv_fwd(4, 1, bad, alm, blm)
+        B.totalconv_fwd_x(4, 1, bad, alm, blm)
     with pytest.raises(ValueError):
-        B.totalconv_fwd(4, 2, x, alm, blm)
+        B.totalconv_fwd_x(4, 2, x, alm, blm)
 
 
 # ------------------------------------------------------------------------ adjoint
@@ -266,7 +266,7 @@ def test_adj_vs_oracle_full(B, orc, L, M, nring):
     blm = S.random_beam(L, M, 22)
     G = S.random_cbar(L, M, nring, 23)
     say(f"totalconv_adj L={L} M={M} nring={nring}")
-    ga, gb = B.totalconv_adj(L, M, x, dev(alm), dev(blm), dev(G))
+    ga, gb = B.totalconv_adj_x(L, M, x, dev(alm), dev(blm), dev(G))
     ra, rb = orc.totalconv_adj(L, M, x, alm, blm, G)
     ea = rel_norm(ga.cpu().numpy(), ra)
     gbn = gb.cpu().numpy()
@@ -285,8 +285,8 @@ def test_adj_dot_product_medium(B):
     blm = dev(S.random_beam(L, M, 32))
     G = dev(S.random_cbar(L, M, nring, 33))
     say(f"dot product L={L} M={M} nring={nring}")
-    C = B.totalconv_fwd(L, M, x, alm, blm)
-    ga, gb = B.totalconv_adj(L, M, x, alm, blm, G)
+    C = B.totalconv_fwd_x(L, M, x, alm, blm)
+    ga, gb = B.totalconv_adj_x(L, M, x, alm, blm, G)
     lhs = torch.vdot(G.flatten(), C.flatten()).item()
     rhs_a = torch.vdot(ga.flatten(), alm.flatten()).item()
     rhs_b = torch.sum(torch.conj(blm) * gb).item()
@@ -300,22 +300,24 @@ def test_adj_dot_product_medium(B):
                                          ("lmax4096", [0, 9, 3000, 4096], (8, 32, 4))])
 def test_adj_large_sampled_sky_gradient(B, orc, name, msel, t):
     """Forward + adjoint at full size (lmax 2048 / 4096, the latter being the benchmark's
-    launch, at each adjoint tile its autotuning picks) with loss 0.5||C - C_target||^2; the oracle
-    evaluates the sky gradient for sampled msky (every mb and ring of those columns); the
+    launch, at each adjoint tile its autotuning picks) with a seeded Gaussian cotangent drawn on
+    the device by torch's generator; the oracle evaluates the sky gradient for sampled msky
+    (every mb and ring of those columns, their cotangent rows copied back), and the
     dot-product identities <G, C> = <sky_bar, a> = <b, beam_bar> check the whole of both
-    gradients."""
+    gradients.  (The loss 0.5||C - C_target||^2 of the adjoint workload is the cotangent of
+    test_autograd_finite_differences_adjoint_workload.)"""
     w = S.WORKLOADS[name]
     x, alm, blm = w.xring(), w.alm(), w.blm()
-    target = S.sky_alm(w.lmax, w.target_seed)
     say(f"adjoint workload L={w.lmax} M={w.mbmax} nring={w.nring} adjoint tile {t or 'built-in'}")
     a_d, b_d = dev(alm), dev(blm)
-    C = B.totalconv_fwd(w.lmax, w.mbmax, x, a_d, b_d)
-    T = B.totalconv_fwd(w.lmax, w.mbmax, x, dev(target), b_d)
-    G = C - T
+    C = B.totalconv_fwd_x(w.lmax, w.mbmax, x, a_d, b_d)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w.lmax + 17)
+    G = torch.randn(C.shape, dtype=torch.complex128, device="cuda", generator=gen)
     lhs = torch.vdot(G.flatten(), C.flatten()).item()
-    del C, T
+    del C
     with tile(B, B.TC_OP_ADJ, t):
-        ga, gb = B.totalconv_adj(w.lmax, w.mbmax, x, a_d, b_d, G)
+        ga, gb = B.totalconv_adj_x(w.lmax, w.mbmax, x, a_d, b_d, G)
     rhs_a = torch.vdot(ga.flatten(), a_d.flatten()).item()
     rhs_b = torch.sum(torch.conj(b_d) * gb).item()
     say(f"  <G,C>={lhs:.9e}  <ga,a>={rhs_a:.9e}  <b,gb>={rhs_b:.9e}")
@@ -345,7 +347,7 @@ def test_adj_large_sampled_sky_gradient(B, orc, name, msel, t):
 # ------------------------------------------------------------------------ autograd
 
 def test_autograd_central_differences(B):
-    from paper_1002_1050_amd import TotalConv
+    from paper_1002_1050_amd import TotalConvX as TotalConv
     L, M, nring = 24, 3, 49
     x = S.ring_cosines(nring)
     alm = dev(S.sky_alm(L, 41) + 0.0j).requires_grad_(True)
@@ -396,7 +398,7 @@ def test_autograd_finite_differences_adjoint_workload(B):
     is the one that balances the two rounding errors of a central difference: the residual's
     size in that mb row over the size of the coefficient's own response (a forward call with
     the unit coefficient).  The gate is 1e-6 x max|g| (over the sky, resp. the beam, gradient)."""
-    from paper_1002_1050_amd import TotalConv
+    from paper_1002_1050_amd import TotalConvX as TotalConv
     w = S.WORKLOADS["adjoint"]
     L, M = w.lmax, w.mbmax
     x = w.xring()
@@ -405,7 +407,7 @@ def test_autograd_finite_differences_adjoint_workload(B):
     blm = dev(blm_h).requires_grad_(True)
     say(f"autograd finite differences L={L} M={M} nring={x.size}")
     with torch.no_grad():
-        T = B.totalconv_fwd(L, M, x, dev(S.sky_alm(L, w.target_seed)), blm.detach())
+        T = B.totalconv_fwd_x(L, M, x, dev(S.sky_alm(L, w.target_seed)), blm.detach())
     C = TotalConv.apply(alm, blm, x, L, M)
     loss = 0.5 * torch.sum(torch.abs(C - T) ** 2)
     loss.backward()
@@ -418,8 +420,8 @@ def test_autograd_finite_differences_adjoint_workload(B):
 
     def central(da, db, h):
         # (L(p + h) - L(p - h)) / 2h with |Cp - T|^2 - |Cm - T|^2 = Re((Cp - Cm) conj(Cp + Cm - 2T))
-        B.totalconv_fwd(L, M, x, a0 + da, b0 + db, out=Cp)
-        B.totalconv_fwd(L, M, x, a0 - da, b0 - db, out=Cm)
+        B.totalconv_fwd_x(L, M, x, a0 + da, b0 + db, out=Cp)
+        B.totalconv_fwd_x(L, M, x, a0 - da, b0 - db, out=Cm)
         return 0.5 * torch.sum(((Cp - Cm) * torch.conj(Cp + Cm - 2.0 * T)).real).item() / (2.0 * h)
 
     rng = np.random.Generator(np.random.PCG64(7))
@@ -443,7 +445,7 @@ def test_autograd_finite_differences_adjoint_workload(B):
             l = int(rng.integers(abs(r - M), L + 1))
             unit_b = zb.clone()
             unit_b[r, l] = 1.0
-            B.totalconv_fwd(L, M, x, a0, unit_b, out=Cp)
+            B.totalconv_fwd_x(L, M, x, a0, unit_b, out=Cp)
             h = R[r].abs().max().item() / Cp[r].abs().max().item()
             for unit in (1.0, 1j):
                 d = zb.clone()

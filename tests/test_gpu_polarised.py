@@ -63,8 +63,8 @@ def test_polarised_forward_separate_and_summed(B, orc, R, TB, npair):
         da, db = [dev(a) for a in alms], [dev(b) for b in blms]
         B.set_tile_ex(B.TC_OP_FWD_POL, R, TB, 0)
         say(f"fwd_pol L={L} M={M} nring={n} npair={npair} R={R} TB={TB}")
-        sep = [c.cpu().numpy() for c in B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SEPARATE)]
-        tot = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
+        sep = [c.cpu().numpy() for c in B.totalconv_fwd_pol_x(L, M, x, da, db, B.TC_POL_SEPARATE)]
+        tot = B.totalconv_fwd_pol_x(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
         ref = orc.totalconv_fwd_pol(L, M, x, alms, blms)
         gs = max(column_gate(sep[p], ref[p]) for p in range(npair))
         gt = column_gate(tot, sum(ref))
@@ -75,7 +75,7 @@ def test_polarised_forward_separate_and_summed(B, orc, R, TB, npair):
         # random beams), where the scalar forward sums even and odd l apart
         B.set_tile_ex(B.TC_OP_FWD, R, TB, 0)
         for p in range(npair):
-            plain = B.totalconv_fwd(L, M, x, da[p], db[p]).cpu().numpy()
+            plain = B.totalconv_fwd_x(L, M, x, da[p], db[p]).cpu().numpy()
             rows = [r for r in range(2 * M + 1) if r != M]
             assert np.array_equal(plain[rows], sep[p][rows]), f"pair {p}: polarised output != scalar forward"
             assert column_gate(plain[M], sep[p][M]) <= 1e-13
@@ -87,7 +87,7 @@ def test_polarised_single_pair_is_scalar(B, orc):
     alms, blms = pairs(L, M, 1, 7)
     da, db = [dev(alms[0])], [dev(blms[0])]
     say("fwd_pol npair=1")
-    got = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
+    got = B.totalconv_fwd_pol_x(L, M, x, da, db, B.TC_POL_SUM)[0].cpu().numpy()
     ref = orc.totalconv_fwd(L, M, x, alms[0], blms[0])
     assert column_gate(got, ref) <= GATE
 
@@ -102,7 +102,7 @@ def test_polarised_adjoint(B, orc, summed):
     Gs = [S.random_cbar(L, M, n, 500 + k) for k in range(nG)]
     mode = B.TC_POL_SUM if summed else B.TC_POL_SEPARATE
     say(f"adj_pol L={L} M={M} nring={n} summed={summed}")
-    ga, gb = B.totalconv_adj_pol(L, M, x, da, db, [dev(g) for g in Gs], mode)
+    ga, gb = B.totalconv_adj_pol_x(L, M, x, da, db, [dev(g) for g in Gs], mode)
     ra, rb = orc.totalconv_adj_pol(L, M, x, alms, blms, Gs, summed=summed)
     for p in range(3):
         a = ga[p].cpu().numpy()
@@ -113,7 +113,7 @@ def test_polarised_adjoint(B, orc, summed):
         say(f"  pair {p}: sky {ea:.2e}, beam {eb:.2e}")
         assert ea <= GATE and eb <= GATE
     # only the beam gradients requested: the sky arrays stay untouched (None)
-    ga2, gb2 = B.totalconv_adj_pol(L, M, x, da, db, [dev(g) for g in Gs], mode, want_alm=False)
+    ga2, gb2 = B.totalconv_adj_pol_x(L, M, x, da, db, [dev(g) for g in Gs], mode, want_alm=False)
     assert all(g is None for g in ga2)
     for p in range(3):
         assert torch.equal(gb2[p], gb[p])
@@ -127,13 +127,13 @@ def test_polarised_rejects_bad_arguments(B):
     lib = B.lib()
     arr = B._ptr_array
     out = [torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda") for _ in range(4)]
-    ws = torch.empty(B.workspace_bytes(B.TC_OP_FWD_POL, L, M, x), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(B.workspace_bytes_x(B.TC_OP_FWD_POL, L, M, x), dtype=torch.uint8, device="cuda")
     xp = x.ctypes.data_as(B.ctypes.c_void_p)
     for npair, mode in ((4, 0), (0, 0), (2, 2)):
-        rc = lib.totalconv_fwd_pol(L, M, x.size, xp, npair, arr(da + da), arr(db + db), mode, arr(out),
+        rc = lib.totalconv_fwd_pol_x(L, M, x.size, xp, npair, arr(da + da), arr(db + db), mode, arr(out),
                                    B._dptr(ws), ws.numel(), None)
         assert rc == -1, (npair, mode)
-    rc = lib.totalconv_fwd_pol(L, M, x.size, xp, 3, arr(da[:2] + [None]), arr(db), 0, arr(out),
+    rc = lib.totalconv_fwd_pol_x(L, M, x.size, xp, 3, arr(da[:2] + [None]), arr(db), 0, arr(out),
                                B._dptr(ws), ws.numel(), None)
     assert rc == -1 and "pair 2" in B.last_error()
 
@@ -142,7 +142,7 @@ def test_polarised_rejects_bad_arguments(B):
 def test_polarised_autograd_central_differences(B, summed):
     """TotalConvPol's backward (the polarised adjoint) against central differences of a quadratic
     loss, for every pair's sky and beam."""
-    from paper_1002_1050_amd.autograd import TotalConvPol
+    from paper_1002_1050_amd.autograd import TotalConvPolX as TotalConvPol
     L, M, n = 20, 2, 41
     x = S.ring_cosines(n)
     mode = B.TC_POL_SUM if summed else B.TC_POL_SEPARATE
@@ -201,11 +201,11 @@ def test_polarised_full_size_sampled(B, orc):
     ms = np.minimum(ms, L)
     idx = torch.from_numpy(((mb + M) * (L + 1) + ms).astype(np.int64)).to("cuda")
     say(f"fwd_pol full size L={L} M={M} nring={x.size}, three pairs")
-    sep = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SEPARATE)
+    sep = B.totalconv_fwd_pol_x(L, M, x, da, db, B.TC_POL_SEPARATE)
     got = [c.reshape(-1, x.size).index_select(0, idx).cpu().numpy() for c in sep]
     del sep
     torch.cuda.empty_cache()
-    tot = B.totalconv_fwd_pol(L, M, x, da, db, B.TC_POL_SUM)[0]
+    tot = B.totalconv_fwd_pol_x(L, M, x, da, db, B.TC_POL_SUM)[0]
     got_t = tot.reshape(-1, x.size).index_select(0, idx).cpu().numpy()
     del tot
     torch.cuda.empty_cache()

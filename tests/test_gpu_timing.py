@@ -20,10 +20,10 @@ def test_kernel_timing_records_each_call():
     print(f"[gpu] timing events, lmax {L}", flush=True)
     B.timing_enable(3)
     try:
-        C0 = B.totalconv_fwd(L, M, x, alm, blm)
+        C0 = B.totalconv_fwd_x(L, M, x, alm, blm)
         for _ in range(3):
-            C = B.totalconv_fwd(L, M, x, alm, blm)
-        B.totalconv_adj(L, M, x, alm, blm, G)
+            C = B.totalconv_fwd_x(L, M, x, alm, blm)
+        B.totalconv_adj_x(L, M, x, alm, blm, G)
         torch.cuda.synchronize()
         f = B.timing_read(B.TC_OP_FWD, 8)
         a = B.timing_read(B.TC_OP_ADJ, 8)

@@ -271,3 +271,36 @@ def test_invalid_arguments(orc):
         orc.wigner_d(5, [0], [0], np.array([1.5]))     # |x| > 1 is not a ring
     with pytest.raises(ValueError):
         orc.wigner_d(5, [0], [-6], np.array([0.1]))
+
+
+# ------------------------------------------------------------------- ring definition
+
+def test_ring_x_is_cos_rounded_once(orc):
+    """oracle.ring_x(beta) = cos(beta) rounded once to double (the ring definition x_j of the
+    boundary; Sec. 4.2.2 precomputes cos(beta) per ring).  Reference: mpmath cos at 50 digits,
+    rounded to nearest.  The oracle evaluates cosl in x87 long double and rounds that to double,
+    so it may differ from the correctly rounded value only where the exact cosine lies within
+    half a long-double ulp of a midpoint between two doubles (double rounding); any other
+    difference is an error."""
+    mp.mp.dps = 50
+    rng = np.random.Generator(np.random.PCG64(1050))
+    beta = np.concatenate([
+        [0.0, np.pi, np.pi / 2, np.nextafter(np.pi, 0.0), np.nextafter(0.0, 1.0), 1e-300, 1e-9,
+         np.pi - 1e-9, np.nextafter(np.pi / 2, 0.0), np.nextafter(np.pi / 2, 4.0)],
+        rings(7), rings(64), rings(1025),
+        rng.uniform(0.0, np.pi, 3000),
+        rng.uniform(0.0, 1e-4, 200), np.pi - rng.uniform(0.0, 1e-4, 200),
+        np.pi / 2 + rng.uniform(-1e-6, 1e-6, 200)])
+    x = orc.ring_x(beta)
+    mism = 0
+    for b, xv in zip(beta, x):
+        exact = mp.cos(mp.mpf(float(b)))
+        cr = float(exact)                       # mpmath -> float rounds to nearest
+        if xv == cr:
+            continue
+        mism += 1
+        # double rounding only: the exact value sits within 2^-64 |x| of the midpoint
+        assert abs(np.nextafter(cr, xv) - xv) == 0.0 or abs(xv - cr) <= abs(np.nextafter(cr, xv) - cr)
+        mid = (mp.mpf(float(cr)) + mp.mpf(float(xv))) / 2
+        assert abs(exact - mid) <= mp.mpf(2) ** -64 * abs(exact), (b, xv, cr)
+    assert mism <= 3, f"{mism} double-rounding cases out of {beta.size}"
