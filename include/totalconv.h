@@ -176,6 +176,24 @@ int totalconv_fwd_x(int lmax, int mbmax, int nring, const double* cosbeta,
                     void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): totalconv_fwd without a
+ * workspace argument.  Its tables (ring tables, column list, seed normalisations,
+ * beam-row signs) live in a static device array of the library, one per GPU,
+ * TC_NOALLOC_SCRATCH_BYTES (8 MiB) long and held until the process ends: enough for
+ * lmax 4096 with mbmax 14 on 8192 rings, or lmax 8192 with mbmax 16 on 16384 rings.
+ * Allocates no device or pinned memory (no hipMalloc, hipFree or hipHostMalloc): the
+ * tables are built on the host and copied on `stream` from pageable memory.  All
+ * calls on one GPU share its array and the last call's contents stay in it; calls
+ * that overlap on one GPU (several streams or threads) race and must be serialised.
+ * TC_ENOMEM when the tables would exceed the array; otherwise the arguments, checks
+ * and results of totalconv_fwd, whose kernels it runs (equal bit for bit).
+ */
+#define TC_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int totalconv_fwd_noalloc(int lmax, int mbmax, int nring, const double* beta,
+                          const double* alm, const double* blm, double* C, void* stream);
+
+/*
  * Adjoint of totalconv_fwd (not in the paper; the exact transpose of eq. convdef).
  * With Cbar = dL/dconj(C) (the layout of C; PyTorch's gradient convention),
  *   alm_bar_{l,msky} = sum_{mb,j} b_{l,mb} d^l_{mb,msky}(beta_j) Cbar_{mb,msky,j}

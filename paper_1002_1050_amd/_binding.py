@@ -72,6 +72,8 @@ def lib():
                     getattr(L, n).argtypes = args
             L.tc_rings_from_beta.restype = I
             L.tc_rings_from_beta.argtypes = [I, P, P]
+            L.totalconv_fwd_noalloc.restype = I
+            L.totalconv_fwd_noalloc.argtypes = [I, I, I, P, P, P, P, P]
             L.tc_set_tile.restype = I
             L.tc_set_tile.argtypes = [I, I]
             L.tc_get_tile.restype = I
@@ -279,6 +281,22 @@ def _totalconv_fwd(lmax, mbmax, rings, cos, alm, blm, out):
 def totalconv_fwd(lmax: int, mbmax: int, beta, alm, blm, out=None):
     """C = totalconv(alm, blm) on the colatitudes beta; complex128 (2*mbmax+1, lmax+1, nring)."""
     return _totalconv_fwd(lmax, mbmax, beta, False, alm, blm, out)
+
+
+def totalconv_fwd_noalloc(lmax: int, mbmax: int, beta, alm, blm, out):
+    """totalconv_fwd with its tables in the library's static device array (no workspace, no
+    allocation by the library); `out` must be given, complex128 (2*mbmax+1, lmax+1, nring)."""
+    import torch
+    device = _sky_beam(torch, lmax, mbmax, alm, blm)
+    b = _host(beta, np.float64)
+    shape = (2 * mbmax + 1, lmax + 1, b.size)
+    _require_device(out, "out", torch.complex128)
+    if tuple(out.shape) != shape or out.device != device:
+        raise ValueError(f"out must have shape {shape} on {device}")
+    rc = lib().totalconv_fwd_noalloc(lmax, mbmax, b.size, _hptr(b), _dptr(alm), _dptr(blm), _dptr(out),
+                                     _stream_handle(torch, device))
+    _check("totalconv_fwd_noalloc", rc)
+    return out
 
 
 def totalconv_fwd_x(lmax: int, mbmax: int, cosbeta, alm, blm, out=None):

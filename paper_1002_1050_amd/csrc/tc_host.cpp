@@ -417,7 +417,8 @@ int check_grid(const Layout& L)
 
 // Forward for npair (sky, beam) pairs: one output per pair, or (sum) one output.
 int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int npair, const double* const* alm,
-             const double* const* blm, int sum, double* const* C, void* workspace, size_t ws_bytes, void* stream)
+             const double* const* blm, int sum, double* const* C, void* workspace, size_t ws_bytes, void* stream,
+             bool cached = true)
 {
     int rc = check_sizes(lmax, mbmax);
     if (rc || (rc = check_rings(nring, cosbeta))) return rc;
@@ -433,12 +434,18 @@ int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int 
     const tc::Tile t = default_tile(op, lmax);
     const Layout L = make_layout(op, lmax, mbmax, nring, cosbeta, t);
     if ((rc = check_ws(L, workspace, ws_bytes)) || (rc = check_grid(L))) return rc;
-    rc = upload_tables(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 0, nullptr, nullptr, L, t, workspace, stream,
-                       [&](std::vector<char>& img) {
-                           build_rings(nring, cosbeta, img, L);
-                           build_slots(nring, cosbeta, img, L);
-                           build_columns(lmax, mbmax, img, L);
-                       });
+    auto build = [&](std::vector<char>& img) {
+        build_rings(nring, cosbeta, img, L);
+        build_slots(nring, cosbeta, img, L);
+        build_columns(lmax, mbmax, img, L);
+    };
+    if (cached) {
+        rc = upload_tables(TC_OP_FWD, lmax, mbmax, nring, cosbeta, 0, nullptr, nullptr, L, t, workspace, stream, build);
+    } else {   // no pinned image: built here and copied from pageable host memory
+        std::vector<char> img(L.tables_end, 0);
+        build(img);
+        rc = upload(workspace, img, stream);
+    }
     if (rc) return rc;
     tc::FwdArgs a{};
     a.lmax = lmax; a.mbmax = mbmax; a.nring = nring; a.nslot = L.nslot; a.ncol = L.ncol; a.ntile = L.ntile;
@@ -980,6 +987,29 @@ int totalconv_adj_pol(int lmax, int mbmax, int nring, const double* beta, int np
 }
 
 }  // extern "C"
+
+// ============================================================ no-allocation forward
+namespace tc {
+
+int fail_hip(int rc, const char* what) { return hip_fail(rc, what); }
+
+int fwd_noalloc(int lmax, int mbmax, int nring, const double* beta, const double* alm, const double* blm, double* C,
+                void* scratch, size_t scratch_bytes, void* stream)
+{
+    g_error.clear();
+    std::vector<double> x;
+    int rc = rings_from_beta(nring, beta, x);
+    if (rc) return rc;
+    if ((rc = check_sizes(lmax, mbmax))) return rc;
+    const Layout L = make_layout(TC_OP_FWD, lmax, mbmax, nring, x.data(), default_tile(TC_OP_FWD, lmax));
+    if (L.total > scratch_bytes)
+        return fail(TC_ENOMEM, "totalconv_fwd_noalloc: the tables need %zu bytes, more than the %zu bytes of "
+                               "its static device array", L.total, scratch_bytes);
+    return fwd_impl(TC_OP_FWD, lmax, mbmax, nring, x.data(), 1, &alm, &blm, 0, &C, scratch, scratch_bytes, stream,
+                    false);
+}
+
+}  // namespace tc
 
 // ===================================================================== plans
 //

@@ -126,4 +126,12 @@ int launch_adj_beam(const EpiArgs& e, void* stream);
 int queue_occupancy(int op, Tile t, bool rows, int* blocks_per_cu);
 bool tile_supported(int op, Tile t);
 
+// The forward on colatitudes with its tables in `scratch` (scratch_bytes) instead of a caller
+// workspace, copied from pageable host memory (no pinned cache, no allocation of device or pinned
+// memory); TC_ENOMEM when the tables do not fit (tc_host.cpp).
+int fwd_noalloc(int lmax, int mbmax, int nring, const double* beta, const double* alm, const double* blm, double* C,
+                void* scratch, size_t scratch_bytes, void* stream);
+// Records a failed HIP call as the calling thread's last error and returns TC_EHIP (tc_host.cpp).
+int fail_hip(int rc, const char* what);
+
 }  // namespace tc
