@@ -110,6 +110,10 @@ def parse():
                    help="timed repetitions of the data-cube stage on the forward's output (0 skips)")
     p.add_argument("--matrix-reps", type=int, default=2,
                    help="timed repetitions of the full-matrix generator at l = lmax on 16 rings (0 skips)")
+    p.add_argument("--config-reps", type=int, default=5,
+                   help="timed repetitions of the lmax 64 / 1024 / 2048 workloads (0 skips)")
+    p.add_argument("--large-reps", type=int, default=3,
+                   help="timed repetitions of one 4096-ring chunk of the four lmax 8192 detectors (0 skips)")
     p.add_argument("--no-tune", action="store_true", help="use the built-in tiles instead of the autotuner")
     p.add_argument("--tile-fwd", default="", help="forward tile 'R,TB' (skips its autotuning)")
     p.add_argument("--tile-adj", default="", help="adjoint tile 'R,TB[,TR]' (skips its autotuning)")
@@ -147,11 +151,14 @@ def cpu_baseline(w, x, alm, blm, G_cols_fn, seconds):
         ncols += sel.size
         if elapsed >= seconds:
             break
+    rate = done_terms / elapsed
     return {
-        "value": done_terms / elapsed,
+        "value": rate,
         "unit": "terms/s",
         "cores": int(oracle.max_threads()),
         "kind": "oracle",
+        # the whole workload (forward + adjoint over every column) at the sampled rate
+        "full_workload_extrapolated_s": round(2 * w.terms() / rate, 1),
         "sample": f"{ncols} seeded random (mb, msky) columns x all {w.nring} rings of the {w.name} "
                   f"workload, forward + adjoint column sums, x87 long double, {elapsed:.1f} s; "
                   f"{host_cpu()}",
@@ -343,6 +350,131 @@ def batched_adjoint_compare(w, dets, plain, alm, reps, tune):
     }
     plan.close()
     return res
+
+
+def config_timing(name, reps, tune):
+    """One plain workload (small, medium, adjoint): forward and adjoint through the entry points on
+    colatitudes, timed with the library's HIP events around each recursion kernel (median of reps
+    after one warm-up; the adjoint's kernel time is its launches over the ring tiles) and as whole
+    calls; cotangent a seeded Gaussian drawn on the device."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import synthetic as S
+    w = S.WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    beta = w.colatitudes()
+    x = B.rings_from_beta(beta)
+    alm = torch.from_numpy(w.alm()).to(dev)
+    blm_h = w.blm()
+    blm = torch.from_numpy(blm_h).to(dev)
+    C = torch.empty((2 * w.mbmax + 1, w.lmax + 1, w.nring), dtype=torch.complex128, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(w.lmax)
+    G = torch.randn(C.shape, dtype=torch.complex128, device=dev, generator=gen)
+    tf = ta = (0, 0, 0)
+    if tune:
+        from paper_1002_1050_amd import autotune
+        tf = autotune.tune_plain(B.TC_OP_FWD, w.lmax, w.mbmax, x, alm, blm, reps=1)
+        ta = autotune.tune_plain(B.TC_OP_ADJ, w.lmax, w.mbmax, x, alm, blm, G, reps=1)
+    B.set_tile_ex(B.TC_OP_FWD, *tf)
+    B.set_tile_ex(B.TC_OP_ADJ, *ta)
+    s = torch.cuda.current_stream(dev)
+    B.totalconv_fwd(w.lmax, w.mbmax, beta, alm, blm, out=C)
+    B.totalconv_adj(w.lmax, w.mbmax, beta, alm, blm, G)
+    torch.cuda.synchronize()
+    B.timing_enable(reps)
+    fwd, adj = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        B.totalconv_fwd(w.lmax, w.mbmax, beta, alm, blm, out=C)
+        e[1].record(s)
+        B.totalconv_adj(w.lmax, w.mbmax, beta, alm, blm, G)
+        e[2].record(s)
+        torch.cuda.synchronize()
+        fwd.append(e[0].elapsed_time(e[1]))
+        adj.append(e[1].elapsed_time(e[2]))
+    kf = float(np.median(B.timing_read(B.TC_OP_FWD, reps)))
+    ka = float(np.median(B.timing_read(B.TC_OP_ADJ, reps)))
+    B.timing_enable(0)
+    B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
+    B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
+    terms = w.terms()
+    fpt_f = forward_flops_per_term(w, blm_h, True)
+    fpt_a = FLOPS_PER_TERM_PAIRED
+    cf, ca = float(np.median(fwd)), float(np.median(adj))
+    res = {"workload": f"lmax={w.lmax}, mbmax={w.mbmax}, {w.nring} rings, forward + adjoint", "terms_per_pass": terms,
+           "tiles_R_TB_TR": {"forward": list(tf), "adjoint": list(ta)},
+           "forward_call_ms": round(cf, 4), "adjoint_call_ms": round(ca, 4),
+           "forward_kernel_ms": round(kf, 4), "adjoint_kernel_ms": round(ka, 4),
+           "terms_per_s": 2 * terms / ((cf + ca) * 1e-3),
+           "forward_frac": round(fpt_f * terms / (kf * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+           "adjoint_frac": round(fpt_a * terms / (ka * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+           "reps": reps}
+    log(f"  {name}: forward {cf:.3f} ms (kernel {kf:.3f}), adjoint {ca:.3f} ms (kernel {ka:.3f}), "
+        f"{res['terms_per_s']:.3e} terms/s, frac {res['forward_frac']} / {res['adjoint_frac']}")
+    del C, G
+    torch.cuda.empty_cache()
+    return res
+
+
+def large_chunk_timing(reps, chunk=1):
+    """The four lmax 8192 detectors (mbmax 16, 16384 rings) on one chunk of 4096 rings (2048 mirror
+    pairs; the chunk next to the polar one by default): the batched forward plan and the batched
+    adjoint plan (sky gradient summed over the detectors, every beam gradient), each forward
+    output as its own cotangent; whole plan executions timed with events on the stream, median
+    of reps after one warm-up."""
+    import torch
+    from paper_1002_1050_amd import _binding as B
+    from paper_1002_1050_amd import synthetic as S
+    w = S.WORKLOADS["large4"]
+    L, M, N, half = w.lmax, w.mbmax, w.nring, 2048
+    dev = torch.device("cuda:0")
+    j = np.arange(N)
+    k = np.minimum(j, N - 1 - j)
+    rings = np.nonzero((k >= chunk * half) & (k < (chunk + 1) * half))[0]
+    beta = w.colatitudes()[rings]
+    alm = torch.from_numpy(w.alm()).to(dev)
+    shape = (2 * M + 1, L + 1, beta.size)
+    dets = [{"lmax": L, "mbmax": M, "beta": beta, "blm": torch.from_numpy(d.blm()).to(dev),
+             "C": torch.empty(shape, dtype=torch.complex128, device=dev)} for d in w.detectors]
+    terms = len(dets) * S.count_terms(L, M, beta.size)
+    s = torch.cuda.current_stream(dev)
+
+    def timed(plan):
+        plan.execute()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            plan.execute()
+            e1.record(s)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return out
+
+    fplan = B.Plan(B.TC_OP_FWD, dets, L, alm)
+    tf = timed(fplan)
+    fplan.close()
+    for d in dets:
+        d["Cbar"] = d.pop("C")
+        d["blm_bar"] = torch.empty_like(d["blm"])
+    alm_bar = torch.empty_like(alm)
+    aplan = B.Plan(B.TC_OP_ADJ, dets, L, alm, alm_bar)
+    ta = timed(aplan)
+    aplan.close()
+    del dets
+    torch.cuda.empty_cache()
+    f, a = float(np.median(tf)), float(np.median(ta))
+    log(f"  large4 chunk {chunk}: forward plan {f:.1f} ms, adjoint plan {a:.1f} ms ({tf} / {ta})")
+    return {"workload": f"four detectors lmax={L}, mbmax={M}, ring chunk {chunk} of 4 ({beta.size} of {N} rings), "
+                        "batched forward and adjoint plans", "terms_per_pass": terms,
+            "forward_ms_median": f, "adjoint_ms_median": a, "forward_ms": tf, "adjoint_ms": ta,
+            "terms_per_s": 2 * terms / ((f + a) * 1e-3),
+            "forward_frac": round(FLOPS_PER_TERM_PAIRED_ROWS * terms / (f * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "adjoint_frac": round(FLOPS_PER_TERM_PAIRED * terms / (a * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "reps": reps}
 
 
 def datacube_timing(w, C, reps):
@@ -656,6 +788,15 @@ def main():
         torch.cuda.empty_cache()
         log("batched sixteen-detector comparison")
         result["batched"] = side_leg("batched comparison", batched_compare, args.batched_reps, not args.no_tune)
+    C = G = None
+    torch.cuda.empty_cache()
+    if args.config_reps > 0:
+        log("the other workloads")
+        result["configs"] = {n: side_leg(f"workload {n}", config_timing, n, args.config_reps, not args.no_tune)
+                             for n in ("small", "medium", "adjoint")}
+    if args.large_reps > 0:
+        log("four lmax 8192 detectors, one ring chunk")
+        result["large4_chunk"] = side_leg("large chunk", large_chunk_timing, args.large_reps)
     print(json.dumps(result), flush=True)
 
 
