@@ -456,13 +456,12 @@ int fwd_impl(int op, int lmax, int mbmax, int nring, const double* cosbeta, int 
     a.col = col_ptrs(workspace, L);
     a.npair = npair;
     a.sum = sum;
-    for (int p = 0; p < npair; ++p) { a.alm[p] = alm[p]; a.blm[p] = blm[p]; }
+    for (int p = 0; p < npair; ++p) { a.alm[p] = alm[p]; a.blm[p] = blm[p]; a.pmbmax[p] = mbmax; }
     for (int c = 0; c < nout; ++c) a.C[c] = C[c];
-    a.beam_sym = nullptr;
     if (npair == 1) {   // scalar convolution: beam rows related by a sign take the even / odd sums
         int* sym = reinterpret_cast<int*>(static_cast<char*>(workspace) + L.sym);
         if ((rc = tc::launch_beam_symmetry(blm[0], lmax, mbmax, sym, stream))) return hip_fail(rc, "beam symmetry launch");
-        a.beam_sym = sym;
+        a.beam_sym[0] = sym;
     }
     rc = timed_launch(op, stream, [&] { return tc::launch_fwd(a, t, stream); });
     return rc ? hip_fail(rc, "totalconv_fwd launch") : TC_OK;
@@ -1013,22 +1012,22 @@ int fwd_noalloc(int lmax, int mbmax, int nring, const double* beta, const double
 
 // ===================================================================== plans
 //
-// A plan holds, in one device allocation, every detector's tables, its
-// kernel-argument record, the (detector, column, tile) work items sorted by
-// cost (longest first), the queue counter and, for the adjoint, the partial
-// sums.  Its graph is: reset counter -> persistent kernel [-> sky-gradient
-// epilogue over all detectors -> per-detector beam-gradient epilogues].
+// A plan holds, in one device allocation, the tables of every walk, the kernel-argument
+// records, the work items sorted by cost (longest first) and, for the adjoint, the partial
+// sums.  Forward walks are groups of up to kMaxPairs detectors that share lmax and rings (one
+// recursion feeds each member's output); every adjoint detector walks alone.  The plan's graph
+// is: [beam row signs ->] one launch over the items (the adjoint: one per ring-tile round)
+// [-> sky-gradient epilogue over all detectors -> per-detector beam-gradient epilogues].
 
 struct tc_plan_s {
     int op = 0;
     int ndet = 0;
+    int nwalk = 0;
     int sky_lmax = 0;
     tc::Tile tile{8, 256, 32, 4};
     void* dmem = nullptr;
     size_t dbytes = 0;
     int nitems = 0;
-    int grid = 0;
-    bool rows = false;   // forward: every beam row pair equal up to a sign when the plan was made
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -1078,6 +1077,34 @@ int check_detector(int i, const tc_detector& d, int op, int lmax_sky)
     return TC_OK;
 }
 
+// Walks of a plan: detectors with the same lmax and the same ring cosines (bit for bit) form
+// one class; each class, ordered by mbmax (largest first, then by index), is cut into walks of
+// at most `per_walk` detectors.  Walks come in the order of their first detector.
+std::vector<std::vector<int>> group_detectors(int ndet, const tc_detector* dets,
+                                              const std::vector<std::vector<double>>& xr, int per_walk)
+{
+    std::vector<std::vector<int>> cls;
+    for (int i = 0; i < ndet; ++i) {
+        bool placed = false;
+        for (auto& c : cls) {
+            const int j = c.front();
+            if (dets[j].lmax == dets[i].lmax && xr[j] == xr[i]) {
+                c.push_back(i);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) cls.push_back({i});
+    }
+    std::vector<std::vector<int>> walks;
+    for (auto& c : cls) {
+        std::stable_sort(c.begin(), c.end(), [&](int a, int b) { return dets[a].mbmax > dets[b].mbmax; });
+        for (size_t k = 0; k < c.size(); k += (size_t)per_walk)
+            walks.emplace_back(c.begin() + k, c.begin() + std::min(c.size(), k + (size_t)per_walk));
+    }
+    return walks;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1098,34 +1125,43 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         if (int rc = check_detector(i, dets[i], op, lmax_sky)) return rc;
         if (int rc = detector_rings(i, dets[i], xr[i])) return rc;
     }
+    const tc::Tile tile = default_tile(op, 1 << 20);   // the batched kernel serves every lmax with one R
+    const std::vector<std::vector<int>> walks =
+        group_detectors(ndet, dets, xr, op == TC_OP_FWD ? tc::fwd_walk_pairs(tile) : 1);
+    const int nwalk = (int)walks.size();
 
     tc_plan_s* p = new tc_plan_s;
     p->op = op;
     p->ndet = ndet;
+    p->nwalk = nwalk;
     p->sky_lmax = lmax_sky;
-    p->tile = default_tile(op, 1 << 20);   // the persistent kernel serves every lmax with one R
+    p->tile = tile;
 
-    // ---- layout of the plan's device memory
-    std::vector<Layout> lay(ndet);
-    std::vector<size_t> base(ndet);
+    // ---- layout of the plan's device memory: per walk the tables of its first detector (the
+    // largest mbmax: its columns cover every member's), per detector its beam row signs
+    std::vector<Layout> lay(nwalk);
+    std::vector<size_t> base(nwalk), sym_off(ndet);
     size_t off = 0;
     long long nitems = 0;
+    for (int w = 0; w < nwalk; ++w) {
+        const tc_detector& d = dets[walks[w][0]];
+        lay[w] = make_layout(op, d.lmax, d.mbmax, d.nring, xr[walks[w][0]].data(), p->tile);
+        base[w] = off;
+        off = align_up(off + lay[w].total);
+        nitems += (long long)lay[w].ncol * lay[w].ntile;
+    }
     for (int i = 0; i < ndet; ++i) {
-        lay[i] = make_layout(op, dets[i].lmax, dets[i].mbmax, dets[i].nring, xr[i].data(), p->tile);
-        base[i] = off;
-        off = align_up(off + lay[i].total);
-        nitems += (long long)lay[i].ncol * lay[i].ntile;
+        sym_off[i] = off;
+        off = align_up(off + sizeof(int) * (size_t)(2 * dets[i].mbmax + 1));
     }
     if (nitems > 0x7fffffffLL / 3) { destroy_plan(p); return fail(TC_EUNSUPPORTED, "too many work items"); }
     const size_t args_off = off;
-    const size_t args_bytes = op == TC_OP_FWD ? sizeof(tc::FwdArgs) * ndet : sizeof(tc::AdjArgs) * ndet;
+    const size_t args_bytes = op == TC_OP_FWD ? sizeof(tc::FwdArgs) * nwalk : sizeof(tc::AdjArgs) * nwalk;
     off = align_up(off + args_bytes);
     const size_t epi_off = off;
     off = align_up(off + sizeof(tc::EpiArgs) * ndet);
     const size_t items_off = off;
     off = align_up(off + sizeof(int) * 3 * (size_t)nitems);
-    const size_t counter_off = off;
-    off = align_up(off + sizeof(int));
     p->dbytes = off;
     p->nitems = (int)nitems;
     int rc = (int)hipMalloc(&p->dmem, p->dbytes);
@@ -1136,44 +1172,52 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     }
     char* dm = static_cast<char*>(p->dmem);
 
-    // ---- tables, argument records, items (host image of everything up to the U/V gaps)
-    std::vector<tc::FwdArgs> fa(op == TC_OP_FWD ? ndet : 0);
-    std::vector<tc::AdjArgs> aa(op == TC_OP_ADJ ? ndet : 0);
+    // ---- tables, argument records, items
+    std::vector<tc::FwdArgs> fa(op == TC_OP_FWD ? nwalk : 0);
+    std::vector<tc::AdjArgs> aa(op == TC_OP_ADJ ? nwalk : 0);
     std::vector<tc::EpiArgs> ea(ndet);
-    struct Item { int det, col, tile; long long cost; };
+    struct Item { int walk, col, tile; long long cost; };
     std::vector<Item> items;
     items.reserve((size_t)nitems);
-    for (int i = 0; i < ndet; ++i) {
-        const tc_detector& d = dets[i];
-        const Layout& L = lay[i];
+    for (int w = 0; w < nwalk; ++w) {
+        const std::vector<int>& mem = walks[w];
+        const tc_detector& d = dets[mem[0]];
+        const Layout& L = lay[w];
         std::vector<char> img(L.tables_end, 0);
-        build_rings(d.nring, xr[i].data(), img, L);
-        build_slots(d.nring, xr[i].data(), img, L);
+        build_rings(d.nring, xr[mem[0]].data(), img, L);
+        build_slots(d.nring, xr[mem[0]].data(), img, L);
         build_columns(d.lmax, d.mbmax, img, L);
-        rc = (int)hipMemcpy(dm + base[i], img.data(), img.size(), hipMemcpyHostToDevice);
+        rc = (int)hipMemcpy(dm + base[w], img.data(), img.size(), hipMemcpyHostToDevice);
         if (rc) { destroy_plan(p); return hip_fail(rc, "plan: table upload"); }
-        void* ws = dm + base[i];
+        void* ws = dm + base[w];
         const int* cms = reinterpret_cast<const int*>(img.data() + L.colms);
         const int* cmb = reinterpret_cast<const int*>(img.data() + L.colmb);
         for (int c = 0; c < L.ncol; ++c) {
             const int len = d.lmax - std::max(std::abs(cmb[c]), cms[c]) + 1;
+            int k = 0;   // members with this column's beam row
+            for (int i : mem) k += dets[i].mbmax >= std::abs(cmb[c]);
             for (int t = 0; t < L.ntile; ++t) {
                 const int slots = std::min(p->tile.NT * p->tile.R, L.nslot - t * p->tile.NT * p->tile.R);
-                items.push_back({i, c, t, (long long)len * slots});
+                // a step costs about 3 + 2k operations per chain (the recursion, k outputs' sums)
+                items.push_back({w, c, t, (long long)len * slots * (3 + 2 * k)});
             }
         }
         if (op == TC_OP_FWD) {
-            tc::FwdArgs& a = fa[i];
+            tc::FwdArgs& a = fa[w];
             a = tc::FwdArgs{};
             a.lmax = d.lmax; a.mbmax = d.mbmax; a.nring = d.nring; a.nslot = L.nslot; a.ncol = L.ncol;
             a.ntile = L.ntile; a.sky_lmax = lmax_sky; a.skip_exp = 100;
             a.ring = ring_ptrs(ws, L, d.nring);
             a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
             a.col = col_ptrs(ws, L);
-            a.npair = 1; a.sum = 0; a.alm[0] = alm; a.blm[0] = d.blm; a.C[0] = d.C;
-            a.beam_sym = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.sym);
+            a.npair = (int)mem.size(); a.sum = 0;
+            for (size_t q = 0; q < mem.size(); ++q) {
+                const tc_detector& m = dets[mem[q]];
+                a.pmbmax[q] = m.mbmax; a.alm[q] = alm; a.blm[q] = m.blm; a.C[q] = m.C;
+                a.beam_sym[q] = reinterpret_cast<const int*>(dm + sym_off[mem[q]]);
+            }
         } else {
-            tc::AdjArgs& a = aa[i];
+            tc::AdjArgs& a = aa[w];
             a = tc::AdjArgs{};
             a.lmax = d.lmax; a.mbmax = d.mbmax; a.nring = d.nring; a.nslot = L.nslot; a.ncol = L.ncol;
             a.ntile = L.ntile; a.skip_exp = 100;
@@ -1184,13 +1228,13 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             a.U = reinterpret_cast<double*>(static_cast<char*>(ws) + L.U);
             a.V = reinterpret_cast<double*>(static_cast<char*>(ws) + L.V);
             a.P = L.P;
-            tc::EpiArgs& e = ea[i];
+            tc::EpiArgs& e = ea[mem[0]];
             e = tc::EpiArgs{};
             e.lmax = d.lmax; e.mbmax = d.mbmax; e.P = L.P; e.sky_lmax = lmax_sky;
             e.U = a.U; e.V = a.V; e.alm = alm; e.blm = d.blm; e.alm_bar = nullptr; e.blm_bar = d.blm_bar;
         }
     }
-    // forward: one queue, longest first.  Adjoint: one round per ring tile index, in order (tile 0
+    // forward: one launch, longest first.  Adjoint: one round per ring tile index, in order (tile 0
     // writes each column's U and V, a later tile adds to them), each round longest first.
     std::stable_sort(items.begin(), items.end(), [op](const Item& a, const Item& b) {
         if (op == TC_OP_ADJ && a.tile != b.tile) return a.tile < b.tile;
@@ -1202,7 +1246,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     round_start.push_back((int)items.size());
     std::vector<int> it3(3 * items.size());
     for (size_t k = 0; k < items.size(); ++k) {
-        it3[3 * k] = items[k].det;
+        it3[3 * k] = items[k].walk;
         it3[3 * k + 1] = items[k].col;
         it3[3 * k + 2] = items[k].tile;
     }
@@ -1213,54 +1257,22 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     if (!rc) rc = (int)hipMemcpy(dm + items_off, it3.data(), sizeof(int) * it3.size(), hipMemcpyHostToDevice);
     if (rc) { destroy_plan(p); return hip_fail(rc, "plan: argument upload"); }
 
-    // ---- forward: read the beam row signs once now; if every row pair of every beam is
-    // equal up to a sign, the queue kernel is built for the even / odd form's register
-    // budget (both variants compute both forms: the signs are taken again on each execution)
-    if (op == TC_OP_FWD) {
-        bool all = true;
-        for (int i = 0; i < ndet && !rc && all; ++i) {
-            int* sym = reinterpret_cast<int*>(dm + base[i] + lay[i].sym);
-            rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, sym, stream);
-            if (!rc) rc = (int)hipStreamSynchronize(static_cast<hipStream_t>(stream));
-            std::vector<int> h(2 * dets[i].mbmax + 1, 0);
-            if (!rc) rc = (int)hipMemcpy(h.data(), sym, sizeof(int) * h.size(), hipMemcpyDeviceToHost);
-            for (int v : h) all = all && (v != 0);
-        }
-        if (rc) { destroy_plan(p); return hip_fail(rc, "plan: beam row signs"); }
-        p->rows = all;
-    }
-
-    // ---- persistent grid: every resident workgroup slot of the device
-    int dev = 0, cus = 0, per_cu = 0;
-    rc = (int)hipGetDevice(&dev);
-    if (!rc) rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (!rc) rc = tc::queue_occupancy(op, p->tile, p->rows, &per_cu);
-    if (rc || cus < 1 || per_cu < 1) { destroy_plan(p); return hip_fail(rc ? rc : 1, "plan: occupancy query"); }
-    p->grid = (int)std::min<long long>((long long)cus * per_cu, std::max(nitems, 1LL));
-
     // ---- capture the graph on a private stream (the caller's stream may be the legacy one)
     hipStream_t cs = nullptr;
     rc = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (rc) { destroy_plan(p); return hip_fail(rc, "plan: capture stream"); }
     rc = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    int* counter = reinterpret_cast<int*>(dm + counter_off);
     const int* d_items = reinterpret_cast<const int*>(dm + items_off);
-    if (!rc) rc = tc::launch_reset_counter(counter, cs);
     for (int i = 0; i < ndet && !rc && op == TC_OP_FWD; ++i)   // beam row signs, on every execution
-        rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax,
-                                      reinterpret_cast<int*>(dm + base[i] + lay[i].sym), cs);
+        rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, reinterpret_cast<int*>(dm + sym_off[i]),
+                                      cs);
     if (!rc && op == TC_OP_FWD)
-        rc = tc::launch_fwd_queue(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, counter,
-                                  p->tile, p->rows, p->grid, cs);
+        rc = tc::launch_fwd_items(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, p->tile, cs);
     if (!rc && op == TC_OP_ADJ) {
-        for (size_t r = 0; r + 1 < round_start.size() && !rc; ++r) {
-            const int n = round_start[r + 1] - round_start[r];
-            if (r > 0) rc = tc::launch_reset_counter(counter, cs);
-            if (!rc)
-                rc = tc::launch_adj_queue(reinterpret_cast<const tc::AdjArgs*>(dm + args_off),
-                                          d_items + 3 * (size_t)round_start[r], n, counter, p->tile,
-                                          std::min(p->grid, n), cs);
-        }
+        for (size_t r = 0; r + 1 < round_start.size() && !rc; ++r)
+            rc = tc::launch_adj_items(reinterpret_cast<const tc::AdjArgs*>(dm + args_off),
+                                      d_items + 3 * (size_t)round_start[r], round_start[r + 1] - round_start[r],
+                                      p->tile, cs);
         if (!rc && alm_bar)
             rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
                                           cs);

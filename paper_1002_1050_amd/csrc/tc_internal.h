@@ -40,20 +40,27 @@ struct WignerArgs {
     double* d;             // [npair][lmax+1][nring]
 };
 
+// (sky, beam) pairs that share one walk of the recursion: the polarised pairs (up to 3) or the
+// detectors of a batched plan that share lmax and rings (up to 4).
+constexpr int kMaxPairs = 4;
+
 struct FwdArgs {
-    int lmax, mbmax, nring, nslot, ncol, ntile;
+    int lmax, mbmax, nring, nslot, ncol, ntile;   // mbmax: of the column table (the largest pmbmax)
     int sky_lmax;          // packing lmax of the sky (>= lmax; detectors may share one sky)
     int skip_exp;          // accumulate from the first l-block that may hold |d| >= 2^-skip_exp; 0 = always
     RingTables ring;
     const int* slots;      // [nslot][2] (ring j, mirror ring or -1)
     ColumnTables col;
-    int npair;             // (sky, beam) pairs: 1 scalar, up to 3 polarised (temperature, gradient, curl)
+    int npair;             // pairs sharing the walk: 1 scalar, up to 3 polarised (temperature, gradient,
+                           // curl), up to kMaxPairs detectors ordered by pmbmax, largest first
     int sum;               // polarised: 1 = one output, the sum over the pairs; 0 = one output per pair
-    const double* alm[3];  // packed sky of each pair (complex)
-    const double* blm[3];  // [2M+1][L+1] complex, per pair
-    double* C[3];          // [2M+1][L+1][nring] complex, per output
-    const int* beam_sym;   // scalar convolution: per beam row mb + M, s = +-1 if b_{l,-mb} = s b_{l,mb}
-                           // for every l >= |mb|, else 0 (from k_beam_symmetry); null: not used
+    int pmbmax[kMaxPairs]; // rows of pair p's beam and output: mb = -pmbmax[p] .. pmbmax[p]
+    const double* alm[kMaxPairs];  // packed sky of each pair (complex)
+    const double* blm[kMaxPairs];  // [2 pmbmax+1][L+1] complex, per pair
+    double* C[kMaxPairs];          // [2 pmbmax+1][L+1][nring] complex, per output
+    const int* beam_sym[kMaxPairs];  // scalar convolution: per beam row mb + pmbmax, s = +-1 if
+                           // b_{l,-mb} = s b_{l,mb} for every l >= |mb|, else 0 (from k_beam_symmetry);
+                           // null: not used (polarised)
 };
 
 struct AdjArgs {
@@ -115,15 +122,13 @@ int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void*
 int launch_adj(const AdjArgs& a, Tile t, void* stream);
 int launch_adj_epilogue(const EpiArgs& e, void* stream);
 
-// Batched (persistent) launches: items = (detector, column, tile) triples in queue order.
-int launch_reset_counter(int* counter, void* stream);
-int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, bool rows, int grid,
-                     void* stream);
-int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
-                     void* stream);
+// Batched launches: one workgroup per item, items = (walk or detector, column, tile) triples.
+int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t, void* stream);
+// Detectors one batched forward walk serves with tile t (at most kMaxPairs).
+int fwd_walk_pairs(Tile t);
+int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, void* stream);
 int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream);
 int launch_adj_beam(const EpiArgs& e, void* stream);
-int queue_occupancy(int op, Tile t, bool rows, int* blocks_per_cu);
 bool tile_supported(int op, Tile t);
 
 // The forward on colatitudes with its tables in `scratch` (scratch_bytes) instead of a caller

@@ -52,6 +52,31 @@ static_assert(RS_STEPS % TS == 0 && GROWTH_BITS_PER_STEP * RS_STEPS < 1023 && SK
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
+// Loads and stores through a pointer taken from a struct in memory (the persistent
+// kernels read their arguments from a device array) are marked as global memory, so that
+// they compile to global rather than flat instructions, with a scalar base where the
+// address is uniform.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+// double2 is a class (its copy takes a generic reference): move it as a native vector
+typedef double native_double2 __attribute__((ext_vector_type(2)));
+template <>
+__device__ __forceinline__ double2 ldg(const double2* p)
+{
+    const native_double2 v = *(const __attribute__((address_space(1))) native_double2*)p;
+    return make_double2(v.x, v.y);
+}
+template <>
+__device__ __forceinline__ void stg(double2* p, double2 v)
+{
+    native_double2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(__attribute__((address_space(1))) native_double2*)p = w;
+}
+
 // Minimum resident waves per SIMD asked of the compiler for R chains per lane
 // (bounds the VGPR budget: 512 / waves).
 template <int R>
@@ -355,7 +380,9 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
 // the direct ring and w2 = (-1)^(l-msky) conj(b^p_{l,-mb}) s^p_{l,msky} for the mirror
 // ring.  Scalar convolution: one pair.  Polarised convolution (footnote of Sec. 4.1):
 // the temperature, gradient and curl pairs share the recursion, each with its own
-// weights (NC = NP outputs) or with their weights summed (one output, NC = 1).
+// weights (NC = NP outputs) or with their weights summed (one output, NC = 1).  Detectors
+// that share lmax and rings share it the same way, one output each (batched plans).
+// Pair p's beam and output rows run over mb = -pmbmax[p] .. pmbmax[p].
 struct RawW {
     double br, bi, b2r, b2i, sr, si;
 };
@@ -366,9 +393,9 @@ __device__ __forceinline__ RawW load_weights_raw(const FwdArgs& a, int p, int l,
     if (l <= a.lmax) {
         const double2* blm = reinterpret_cast<const double2*>(a.blm[p]);
         const double2* alm = reinterpret_cast<const double2*>(a.alm[p]);
-        const double2 b1 = blm[(size_t)(mb + a.mbmax) * (a.lmax + 1) + l];
-        const double2 b2 = blm[(size_t)(-mb + a.mbmax) * (a.lmax + 1) + l];
-        const double2 s = alm[packed_index(a.sky_lmax, l, ms)];
+        const double2 b1 = ldg(blm + (size_t)(mb + a.pmbmax[p]) * (a.lmax + 1) + l);
+        const double2 b2 = ldg(blm + (size_t)(-mb + a.pmbmax[p]) * (a.lmax + 1) + l);
+        const double2 s = ldg(alm + packed_index(a.sky_lmax, l, ms));
         w = RawW{b1.x, b1.y, b2.x, b2.y, s.x, s.y};
     }
     return w;
@@ -400,9 +427,14 @@ __device__ __forceinline__ double4 output_weights(const RawW (&raw)[NP], int c, 
     return w;
 }
 
+// LDS slots of one l: {A, nB, F2, -}, then the general form's {w1r, w1i, w2r, w2i} per output
+// or the even / odd form's {w1r, w1i} of two outputs per slot.
+template <int NC, bool ROWS>
+constexpr int coef_slots() { return ROWS ? 1 + (NC + 1) / 2 : 1 + NC; }
+
 template <int NC, int NP>
 __device__ __forceinline__ void stage_block(const FwdArgs& a, const RawW (&raw)[NP], int l, int mb, int ms,
-                                            double4 (&slot)[1 + NC])
+                                            double4* slot)
 {
     double A, nB, F2;
     recursion_coefs(l, mb, ms, a.lmax, A, nB, F2);
@@ -411,8 +443,54 @@ __device__ __forceinline__ void stage_block(const FwdArgs& a, const RawW (&raw)[
     for (int c = 0; c < NC; ++c) slot[1 + c] = output_weights<NC, NP>(raw, c, l, ms);
 }
 
-template <int R, int NC, bool ACC>
-__device__ __forceinline__ void fwd_steps(const double4 (*cf)[1 + NC], int s0,
+// The even / odd form needs w1 only: b^c_{l,mb} of each output and the sky, which the
+// outputs of one walk share (the pairs' skies are one array).
+template <int NC>
+struct RawRows {
+    double br[NC], bi[NC];
+    double sr, si;
+};
+
+template <int NC, int P0>
+__device__ __forceinline__ RawRows<NC> load_rows_raw(const FwdArgs& a, int l, int mb, int ms)
+{
+    RawRows<NC> w;
+    w.sr = 0.0; w.si = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { w.br[c] = 0.0; w.bi[c] = 0.0; }
+    if (l <= a.lmax) {
+        const double2 s = ldg(reinterpret_cast<const double2*>(a.alm[P0]) + packed_index(a.sky_lmax, l, ms));
+        w.sr = s.x; w.si = s.y;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double2* blm = reinterpret_cast<const double2*>(a.blm[P0 + c]);
+            const double2 b = ldg(blm + (size_t)(mb + a.pmbmax[P0 + c]) * (a.lmax + 1) + l);
+            w.br[c] = b.x; w.bi[c] = b.y;
+        }
+    }
+    return w;
+}
+
+template <int NC>
+__device__ __forceinline__ void stage_block_rows(const FwdArgs& a, const RawRows<NC>& w, int l, int mb, int ms,
+                                                 double4* slot)
+{
+    double A, nB, F2;
+    recursion_coefs(l, mb, ms, a.lmax, A, nB, F2);
+    slot[0] = make_double4(A, nB, F2, 0.0);
+    double wr[NC + 1], wi[NC + 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {   // conj(b) * s, as in pair_weights
+        wr[c] = w.br[c] * w.sr + w.bi[c] * w.si;
+        wi[c] = w.br[c] * w.si - w.bi[c] * w.sr;
+    }
+    wr[NC] = 0.0; wi[NC] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; c += 2) slot[1 + c / 2] = make_double4(wr[c], wi[c], wr[c + 1], wi[c + 1]);
+}
+
+template <int R, int NC, bool ACC, int NS>
+__device__ __forceinline__ void fwd_steps(const double4 (*cf)[NS], int s0,
                                           const double (&x)[R], double (&d)[R], double (&dp)[R],
                                           double (&c1r)[NC][R], double (&c1i)[NC][R],
                                           double (&c2r)[NC][R], double (&c2i)[NC][R])
@@ -446,32 +524,39 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[1 + NC], int s0,
 // Beam rows mb and -mb related by a sign s (b_{l,-mb} = s b_{l,mb}, as for a beam with
 // real coefficients): then w2 = s (-1)^(l-msky) w1, and the direct and mirror sums both
 // follow from the sums of w1 d over the even and over the odd steps of the walk, so a
-// step adds w1 d into one of two sums (2 instead of 4 fused multiply-adds per chain).
-// The step parity is that of t (blocks and groups have even lengths): P0 += at even t,
-// P1 at odd t, in the c1 and c2 registers of the general form.
-template <int R, bool ACC>
-__device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[2], int s0,
+// step adds w1 d into one of two sums (2 instead of 4 fused multiply-adds per chain and
+// output).  The step parity is that of t (blocks and groups have even lengths): P0 += at
+// even t, P1 at odd t, in the c1 and c2 registers of the general form.
+template <int R, int NC, bool ACC, int NS>
+__device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[NS], int s0,
                                                const double (&x)[R], double (&d)[R], double (&dp)[R],
-                                               double (&p0r)[R], double (&p0i)[R],
-                                               double (&p1r)[R], double (&p1i)[R])
+                                               double (&p0r)[NC][R], double (&p0i)[NC][R],
+                                               double (&p1r)[NC][R], double (&p1i)[NC][R])
 {
 #pragma unroll
     for (int t = 0; t < TS; ++t) {
         const double4 k = cf[s0 + t][0];
-        double2 w = make_double2(0.0, 0.0);
+        double wr[NC], wi[NC];
         if (ACC) {
-            const double4 v = cf[s0 + t][1];
-            w = make_double2(v.x, v.y);
+#pragma unroll
+            for (int c = 0; c < NC; c += 2) {
+                const double4 v = cf[s0 + t][1 + c / 2];
+                wr[c] = v.x; wi[c] = v.y;
+                if (c + 1 < NC) { wr[c + 1] = v.z; wi[c + 1] = v.w; }
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ACC) {
-                if ((t & 1) == 0) {
-                    p0r[r] = fma(w.x, d[r], p0r[r]);
-                    p0i[r] = fma(w.y, d[r], p0i[r]);
-                } else {
-                    p1r[r] = fma(w.x, d[r], p1r[r]);
-                    p1i[r] = fma(w.y, d[r], p1i[r]);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if ((t & 1) == 0) {
+                        p0r[c][r] = fma(wr[c], d[r], p0r[c][r]);
+                        p0i[c][r] = fma(wi[c], d[r], p0i[c][r]);
+                    } else {
+                        p1r[c][r] = fma(wr[c], d[r], p1r[c][r]);
+                        p1i[c][r] = fma(wi[c], d[r], p1i[c][r]);
+                    }
                 }
             }
             const double u = fma(x[r], k.x, k.y);
@@ -482,38 +567,40 @@ __device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[2], int s0,
     }
 }
 
-// One (column, ring tile) work item of the forward.  cf per l of the current and the
-// next block: {A, nB, F2, -}, then {w1r, w1i, w2r, w2i} of each output.
-template <int R, int NT, int TB, int NC, int NP, bool ROWS>
-__device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int tile, int rows_sign,
-                                                double4 (&cf)[2][TB][1 + NC])
+// One (column, ring tile) work item of the forward over pairs P0 .. P0 + NP - 1 into outputs
+// P0 .. P0 + NC - 1.  ROWS: the even / odd form, output c with beam row sign rows_sign[c].
+// cf holds the coefficient slots of the current and the next block.
+template <int R, int NT, int TB, int NC, int NP, bool ROWS, int P0, int NS>
+__device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int tile, const int* rows_sign,
+                                                double4 (&cf)[2][TB][NS])
 {
     static_assert(NC == 1 || NC == NP, "one output per pair, or one summed output");
-    static_assert(!ROWS || (NC == 1 && NP == 1), "the even / odd sums serve the scalar convolution");
+    static_assert(!ROWS || NC == NP, "the even / odd form: one output per pair");
+    static_assert(NS >= coef_slots<NC, ROWS>() && P0 + NP <= kMaxPairs, "coefficient slots, pairs");
     const int tid = threadIdx.x;
-    const int mb = a.col.mb[ci], ms = a.col.ms[ci];
+    const int mb = ldg(a.col.mb + ci), ms = ldg(a.col.ms + ci);
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
     const SeedShape sh = seed_shape(mb, ms);
-    const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
+    const double lnAh = ldg(a.col.lnA + 2 * ci), lnAl = ldg(a.col.lnA + 2 * ci + 1);
 
+    // the ring indices of the slots are read again for the stores (not held through the walk)
+    const int s_base = tile * (NT * R) + tid * R;   // a wave: 64 R consecutive ring pairs
     double x[R], d[R], dp[R], c1r[NC][R], c1i[NC][R], c2r[NC][R], c2i[NC][R];
-    int E[R], jd[R], jm[R];
+    int E[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int s = tile * (NT * R) + tid * R + r;   // a wave: 64 R consecutive ring pairs
-        jd[r] = -1; jm[r] = -1;
+        const int s = s_base + r;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             c1r[c][r] = 0.0; c1i[c][r] = 0.0; c2r[c][r] = 0.0; c2i[c][r] = 0.0;
         }
         if (s < a.nslot) {
-            jd[r] = a.slots[2 * s];
-            jm[r] = a.slots[2 * s + 1];
-            const int j = jd[r];
-            x[r] = a.ring.x[j];
-            seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
+            const int j = ldg(a.slots + 2 * s);
+            x[r] = ldg(a.ring.x + j);
+            seed_value(lnAh, lnAl, sh, ldg(a.ring.lch + j), ldg(a.ring.lcl + j), ldg(a.ring.lsh + j),
+                       ldg(a.ring.lsl + j), d[r], E[r]);
         }
     }
     bool scaled = false;
@@ -523,12 +610,26 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
     bool acc_on = (a.skip_exp <= 0);
     const double thr = hot_threshold(a.skip_exp);
 
-    RawW raw[NP];
+    RawW raw[NP];         // general form: the loads of the next block, in flight during a block
+    RawRows<NC> rraw;     // even / odd form
+    auto load_raw = [&](int l) {
+        if constexpr (ROWS) {
+            rraw = load_rows_raw<NC, P0>(a, l, mb, ms);
+        } else {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, P0 + p, l, mb, ms);
+        }
+    };
+    auto stage_raw = [&](int l, double4* slot) {
+        if constexpr (ROWS)
+            stage_block_rows<NC>(a, rraw, l, mb, ms, slot);
+        else
+            stage_block<NC, NP>(a, raw, l, mb, ms, slot);
+    };
     const int st0 = stage_slot<NT, TB>(tid, 0);
     if (st0 >= 0) {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, l0 + st0, mb, ms);
-        stage_block<NC, NP>(a, raw, l0 + st0, mb, ms, cf[0][st0]);
+        load_raw(l0 + st0);
+        stage_raw(l0 + st0, cf[0][st0]);
     }
     __syncthreads();
     constexpr int RS_BLK = rs_block<TB>();   // steps between rescales of scaled chains
@@ -538,10 +639,7 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
         const int lb = l0 + kb * TB;
         const int st = stage_slot<NT, TB>(tid, kb + 1);
         const bool stage = (st >= 0) && (kb + 1 < nblk);
-        if (stage) {   // in flight during the block
-#pragma unroll
-            for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, p, lb + TB + st, mb, ms);
-        }
+        if (stage) load_raw(lb + TB + st);   // in flight during the block
         for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
             if (scaled) {
                 bool any = false;
@@ -568,54 +666,51 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
                 if (!acc_on)
                     fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
                 else if constexpr (ROWS)
-                    fwd_steps_rows<R, true>(cf[buf], s0, x, d, dp, c1r[0], c1i[0], c2r[0], c2i[0]);
+                    fwd_steps_rows<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
                 else
                     fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
             }
         }
-        if (stage) stage_block<NC, NP>(a, raw, lb + TB + st, mb, ms, cf[buf ^ 1][st]);
+        if (stage) stage_raw(lb + TB + st, cf[buf ^ 1][st]);
         __syncthreads();
     }
 
-    const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
-    const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     if constexpr (ROWS) {
         // direct sum P0 + P1; mirror sum s (-1)^(msky + l0) (P0 - P1)
-        const double sg = ((ms + l0) & 1) ? -(double)rows_sign : (double)rows_sign;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double er = c1r[0][r] + c2r[0][r], ei = c1i[0][r] + c2i[0][r];
-            const double mr = sg * (c1r[0][r] - c2r[0][r]), mi = sg * (c1i[0][r] - c2i[0][r]);
-            c1r[0][r] = er; c1i[0][r] = ei; c2r[0][r] = mr; c2i[0][r] = mi;
+        for (int c = 0; c < NC; ++c) {
+            const double sg = ((ms + l0) & 1) ? -(double)rows_sign[c] : (double)rows_sign[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double er = c1r[c][r] + c2r[c][r], ei = c1i[c][r] + c2i[c][r];
+                const double mr = sg * (c1r[c][r] - c2r[c][r]), mi = sg * (c1i[c][r] - c2i[c][r]);
+                c1r[c][r] = er; c1i[c][r] = ei; c2r[c][r] = mr; c2i[c][r] = mi;
+            }
         }
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double2* C = reinterpret_cast<double2*>(a.C[c]);
+        const int M = a.pmbmax[P0 + c];
+        const size_t row_d = ((size_t)(mb + M) * (L + 1) + ms) * (size_t)a.nring;
+        const size_t row_m = ((size_t)(-mb + M) * (L + 1) + ms) * (size_t)a.nring;
+        double2* C = reinterpret_cast<double2*>(a.C[P0 + c]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (jd[r] >= 0) {
-                C[row_d + jd[r]] = make_double2(ldexp(c1r[c][r], E[r]), ldexp(c1i[c][r], E[r]));
-                if (jm[r] >= 0)
-                    C[row_m + jm[r]] = make_double2(ldexp(c2r[c][r], E[r]), ldexp(c2i[c][r], E[r]));
+            const int s = s_base + r;
+            if (s < a.nslot) {
+                const int jd = ldg(a.slots + 2 * s), jm = ldg(a.slots + 2 * s + 1);
+                stg(C + row_d + jd, make_double2(ldexp(c1r[c][r], E[r]), ldexp(c1i[c][r], E[r])));
+                if (jm >= 0)
+                    stg(C + row_m + jm, make_double2(ldexp(c2r[c][r], E[r]), ldexp(c2i[c][r], E[r])));
             }
         }
     }
 }
 
-// A work item takes the even / odd form when the column's beam rows are related by a sign
-// (a wave-uniform choice made once per item).
-template <int R, int NT, int TB, int NC, int NP>
-__device__ __forceinline__ void fwd_column(const FwdArgs& a, int ci, int tile, double4 (&cf)[2][TB][1 + NC])
+// Beam row sign of pair p for row mb (0: the rows are not related by a sign).
+__device__ __forceinline__ int row_sign(const FwdArgs& a, int p, int mb)
 {
-    if constexpr (NC == 1 && NP == 1) {
-        const int s = a.beam_sym ? a.beam_sym[a.col.mb[ci] + a.mbmax] : 0;
-        if (s != 0) {
-            fwd_column_walk<R, NT, TB, 1, 1, true>(a, ci, tile, s, cf);
-            return;
-        }
-    }
-    fwd_column_walk<R, NT, TB, NC, NP, false>(a, ci, tile, 0, cf);
+    return ldg(a.beam_sym[p] + mb + a.pmbmax[p]);
 }
 
 // The scalar forward runs as two launches over every (column, tile): k_fwd_rows takes the
@@ -627,9 +722,10 @@ __global__ void __launch_bounds__(NT, (fwd_min_waves<R, NC, NP>())) k_fwd(const 
     __shared__ double4 cf[2][TB][1 + NC];
     const int ci = blockIdx.x / a.ntile;
     if constexpr (NC == 1 && NP == 1) {
-        if (a.beam_sym && a.beam_sym[a.col.mb[ci] + a.mbmax] != 0) return;
+        if (a.beam_sym[0] && row_sign(a, 0, ldg(a.col.mb + ci)) != 0) return;
     }
-    fwd_column_walk<R, NT, TB, NC, NP, false>(a, ci, blockIdx.x - ci * a.ntile, 0, cf);
+    const int none[NC] = {};
+    fwd_column_walk<R, NT, TB, NC, NP, false, 0>(a, ci, blockIdx.x - ci * a.ntile, none, cf);
 }
 
 template <int R, int NT, int TB>
@@ -637,30 +733,75 @@ __global__ void __launch_bounds__(NT, (rows_min_waves<R>())) k_fwd_rows(const Fw
 {
     __shared__ double4 cf[2][TB][2];
     const int ci = blockIdx.x / a.ntile;
-    const int s = a.beam_sym[a.col.mb[ci] + a.mbmax];
-    if (s == 0) return;
-    fwd_column_walk<R, NT, TB, 1, 1, true>(a, ci, blockIdx.x - ci * a.ntile, s, cf);
+    const int s[1] = {row_sign(a, 0, ldg(a.col.mb + ci))};
+    if (s[0] == 0) return;
+    fwd_column_walk<R, NT, TB, 1, 1, true, 0>(a, ci, blockIdx.x - ci * a.ntile, s, cf);
 }
 
-// Persistent form: each workgroup takes (detector, column, tile) items from a
-// queue ordered longest first until it is empty.  W: resident waves per SIMD asked of
-// the compiler (the general form's budget, or the even / odd form's for plans whose
-// beams had every row pair equal up to a sign when the plan was made; either variant
-// computes both forms).
-template <int R, int NT, int TB, int W>
-__global__ void __launch_bounds__(NT, W) k_fwd_queue(const FwdArgs* __restrict__ dets, const int* __restrict__ items,
-                                                     int nitems, int* __restrict__ counter)
+// Batched form: one workgroup per (walk, column, ring tile) item, the items in order of cost,
+// longest first (workgroups start in index order).  A walk serves the npair <= walk_pairs<R>()
+// detectors that share its lmax and rings, ordered by mbmax, largest first: the first k of them
+// have the column's beam row mb.  When all k have that row pair equal up to a sign, one even /
+// odd walk feeds the k outputs; otherwise each detector takes a walk of its own, in the form a
+// plain call would take, so every output is the one a plain call with this tile writes.
+//
+// Detectors per walk: the even / odd sums take 8 VGPRs per chain and output, so R = 8 chains
+// per lane hold two outputs within the 2-wave budget and R <= 4 hold four.
+template <int R>
+constexpr int walk_pairs() { return R >= 8 ? 2 : 4; }
+
+template <int R>
+constexpr int items_min_waves() { return R >= 4 ? 2 : 3; }
+
+template <int R, int NT, int TB, int NS, int P>
+__device__ __forceinline__ void fwd_item_alone(const FwdArgs& a, int ci, int tile, int k, const int (&s)[kMaxPairs],
+                                               double4 (&cf)[2][TB][NS])
 {
-    __shared__ double4 cf[2][TB][2];
-    __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(next);   // uniform: arguments go to SGPRs
-        __syncthreads();
-        if (it >= nitems) break;
-        const FwdArgs a = dets[items[3 * it]];
-        fwd_column<R, NT, TB, 1, 1>(a, items[3 * it + 1], items[3 * it + 2], cf);
+    if (P < k) {
+        if (s[P] != 0)
+            fwd_column_walk<R, NT, TB, 1, 1, true, P>(a, ci, tile, s + P, cf);
+        else
+            fwd_column_walk<R, NT, TB, 1, 1, false, P>(a, ci, tile, s + P, cf);
+    }
+}
+
+template <int R, int NT, int TB>
+__global__ void __launch_bounds__(NT, (items_min_waves<R>())) k_fwd_items(const FwdArgs* __restrict__ walks,
+                                                                          const int* __restrict__ items)
+{
+    constexpr int K = walk_pairs<R>();
+    static_assert(K == 2 || K == 4, "walk sizes");
+    constexpr int NS = coef_slots<K, true>() > 2 ? coef_slots<K, true>() : 2;
+    __shared__ double4 cf[2][TB][NS];
+    const int* item = items + 3 * (size_t)blockIdx.x;
+    const FwdArgs a = walks[item[0]];
+    const int ci = item[1], tile = item[2];
+    const int mb = ldg(a.col.mb + ci);
+    int k = 0, s[kMaxPairs];
+    bool rows = true;
+#pragma unroll
+    for (int p = 0; p < kMaxPairs; ++p) {
+        s[p] = 0;
+        if (p < K && p < a.npair && a.pmbmax[p] >= abs(mb)) {
+            k = p + 1;
+            s[p] = row_sign(a, p, mb);
+            rows = rows && s[p] != 0;
+        }
+    }
+    if (rows) {
+        if (k == 1) { fwd_column_walk<R, NT, TB, 1, 1, true, 0>(a, ci, tile, s, cf); return; }
+        if (k == 2) { fwd_column_walk<R, NT, TB, 2, 2, true, 0>(a, ci, tile, s, cf); return; }
+        if constexpr (K == 4) {
+            if (k == 3) { fwd_column_walk<R, NT, TB, 3, 3, true, 0>(a, ci, tile, s, cf); return; }
+            fwd_column_walk<R, NT, TB, 4, 4, true, 0>(a, ci, tile, s, cf);
+            return;
+        }
+    }
+    fwd_item_alone<R, NT, TB, NS, 0>(a, ci, tile, k, s, cf);
+    fwd_item_alone<R, NT, TB, NS, 1>(a, ci, tile, k, s, cf);
+    if constexpr (K == 4) {
+        fwd_item_alone<R, NT, TB, NS, 2>(a, ci, tile, k, s, cf);
+        fwd_item_alone<R, NT, TB, NS, 3>(a, ci, tile, k, s, cf);
     }
 }
 
@@ -723,12 +864,12 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int kr = lane & (ROW - 1), row = lane >> 4;
-    const int mb = a.col.mb[ci], ms = a.col.ms[ci];
+    const int mb = ldg(a.col.mb + ci), ms = ldg(a.col.ms + ci);
     const int L = a.lmax;
     const int l0 = max(abs(mb), ms);
     const int n = L - l0 + 1;              // l values of a chain
     const SeedShape sh = seed_shape(mb, ms);
-    const double lnAh = a.col.lnA[2 * ci], lnAl = a.col.lnA[2 * ci + 1];
+    const double lnAh = ldg(a.col.lnA + 2 * ci), lnAl = ldg(a.col.lnA + 2 * ci + 1);
     const double2* Cbar = reinterpret_cast<const double2*>(a.Cbar);
     const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
@@ -742,9 +883,10 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
         g1r[r] = 0.0; g1i[r] = 0.0; g2r[r] = 0.0; g2i[r] = 0.0;
         if (s < a.nslot) {
-            const int j = a.slots[2 * s];
-            x[r] = a.ring.x[j];
-            seed_value(lnAh, lnAl, sh, a.ring.lch[j], a.ring.lcl[j], a.ring.lsh[j], a.ring.lsl[j], d[r], E[r]);
+            const int j = ldg(a.slots + 2 * s);
+            x[r] = ldg(a.ring.x + j);
+            seed_value(lnAh, lnAl, sh, ldg(a.ring.lch + j), ldg(a.ring.lcl + j), ldg(a.ring.lsh + j),
+                       ldg(a.ring.lsl + j), d[r], E[r]);
         }
     }
     // A scaled chain (E < 0, |d| < 2^-900) contributes nothing; its cotangent is
@@ -752,11 +894,11 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     auto load_g = [&](int r) {
         const int s = s_base + r;
         if (s < a.nslot && E[r] == 0) {
-            const int jd = a.slots[2 * s], jm = a.slots[2 * s + 1];
-            const double2 v1 = Cbar[row_d + jd];
+            const int jd = ldg(a.slots + 2 * s), jm = ldg(a.slots + 2 * s + 1);
+            const double2 v1 = ldg(Cbar + row_d + jd);
             g1r[r] = v1.x; g1i[r] = v1.y;
             if (jm >= 0) {
-                const double2 v2 = Cbar[row_m + jm];
+                const double2 v2 = ldg(Cbar + row_m + jm);
                 g2r[r] = v2.x; g2i[r] = v2.y;
             }
         }
@@ -930,7 +1072,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
 #pragma unroll
                 for (int w = 0; w < NW * 4; ++w) v += src[4 * w];
                 double* dst = reinterpret_cast<double*>(c < 2 ? U : V) + 2 * (urow + l0 + o) + (c & 1);
-                *dst = (tile == 0) ? v : *dst + v;
+                stg(dst, (tile == 0) ? v : ldg(dst) + v);
             }
         }
     }
@@ -944,24 +1086,17 @@ __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjA
     adj_column<R, NT, TB, TR>(a, blockIdx.x, a.tile, sh);
 }
 
+// Batched form: one workgroup per (detector, column, ring tile) item of one ring-tile round,
+// the items longest first.
 template <int R, int NT, int TB, int TR>
-__global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_queue(const AdjArgs* __restrict__ dets, const int* __restrict__ items,
-                                                  int nitems, int* __restrict__ counter)
+__global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_items(const AdjArgs* __restrict__ dets,
+                                                                            const int* __restrict__ items)
 {
     __shared__ AdjShared<NT, TB> sh;
-    __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(next);   // uniform: arguments go to SGPRs
-        __syncthreads();
-        if (it >= nitems) break;
-        const AdjArgs a = dets[items[3 * it]];
-        adj_column<R, NT, TB, TR>(a, items[3 * it + 1], items[3 * it + 2], sh);
-    }
+    const int* item = items + 3 * (size_t)blockIdx.x;
+    const AdjArgs a = dets[item[0]];
+    adj_column<R, NT, TB, TR>(a, item[1], item[2], sh);
 }
-
-__global__ void k_reset_counter(int* counter) { counter[0] = 0; }
 
 // u(mb, ms, l) = U[mb] + (-1)^(l-ms) V[-mb], defined for l >= max(|mb|, ms)
 __device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int l, size_t k)
@@ -1112,7 +1247,7 @@ int launch_fwd(const FwdArgs& a, Tile t, void* stream)
     if (a.npair == 1) {
 #define X(r, tb)                                                                              \
     if (t.R == r && t.TB == tb) {                                                             \
-        if (a.beam_sym) {                                                                     \
+        if (a.beam_sym[0]) {                                                                  \
             const int rc = launch_grid(k_fwd_rows<r, 256, tb>, a, blocks, 256, stream);       \
             if (rc) return rc;                                                                \
         }                                                                                     \
@@ -1167,24 +1302,13 @@ int launch_adj_beam(const EpiArgs& e, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_reset_counter(int* counter, void* stream)
+int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t, void* stream)
 {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, (hipStream_t)stream, counter);
-    return (int)hipGetLastError();
-}
-
-int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* counter, Tile t, bool rows, int grid,
-                     void* stream)
-{
+    if (nitems <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
 #define X(r, tb)                                                                                             \
     if (t.R == r && t.TB == tb) {                                                                            \
-        if (rows)                                                                                            \
-            hipLaunchKernelGGL((k_fwd_queue<r, 256, tb, rows_min_waves<r>()>), dim3(grid), dim3(256), 0, s, dets, \
-                               items, nitems, counter);                                                      \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_fwd_queue<r, 256, tb, min_waves<r>()>), dim3(grid), dim3(256), 0, s, dets,  \
-                               items, nitems, counter);                                                      \
+        hipLaunchKernelGGL((k_fwd_items<r, 256, tb>), dim3(nitems), dim3(256), 0, s, walks, items);            \
         return (int)hipGetLastError();                                                                       \
     }
     TC_FWD_VARIANTS(X)
@@ -1192,14 +1316,15 @@ int launch_fwd_queue(const FwdArgs* dets, const int* items, int nitems, int* cou
     return (int)hipErrorInvalidValue;
 }
 
-int launch_adj_queue(const AdjArgs* dets, const int* items, int nitems, int* counter, Tile t, int grid,
-                     void* stream)
+int fwd_walk_pairs(Tile t) { return t.R >= 8 ? walk_pairs<8>() : walk_pairs<4>(); }
+
+int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, void* stream)
 {
+    if (nitems <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
 #define X(r, tb, tr)                                                                                        \
     if (t.R == r && t.TB == tb && t.TR == tr) {                                                             \
-        hipLaunchKernelGGL((k_adj_queue<r, 256, tb, tr>), dim3(grid), dim3(256), 0, s, dets, items, nitems, \
-                           counter);                                                                        \
+        hipLaunchKernelGGL((k_adj_items<r, 256, tb, tr>), dim3(nitems), dim3(256), 0, s, dets, items);      \
         return (int)hipGetLastError();                                                                      \
     }
     TC_ADJ_VARIANTS(X)
@@ -1213,30 +1338,6 @@ int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm
     dim3 grid((sky_lmax + 1 + nt - 1) / nt, sky_lmax + 1);
     hipLaunchKernelGGL(k_adj_sky_multi, grid, dim3(nt), 0, (hipStream_t)stream, eps, ndet, sky_lmax, alm_bar);
     return (int)hipGetLastError();
-}
-
-// Resident workgroups per CU of the persistent kernels (for sizing their grid).
-int queue_occupancy(int op, Tile t, bool rows, int* blocks_per_cu)
-{
-    int n = 0;
-    hipError_t rc = hipErrorInvalidValue;
-    if (op == 1) {
-#define X(r, tb)                                                                                                 \
-        if (t.R == r && t.TB == tb)                                                                              \
-            rc = rows ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb, rows_min_waves<r>()>, \
-                                                                     256, 0)                                    \
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fwd_queue<r, 256, tb, min_waves<r>()>, 256, 0);
-        TC_FWD_VARIANTS(X)
-#undef X
-    } else if (op == 2) {
-#define X(r, tb, tr)                           \
-        if (t.R == r && t.TB == tb && t.TR == tr) \
-            rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_queue<r, 256, tb, tr>, 256, 0);
-        TC_ADJ_VARIANTS(X)
-#undef X
-    }
-    *blocks_per_cu = n;
-    return (int)rc;
 }
 
 }  // namespace tc

@@ -1,4 +1,4 @@
-"""Batched plans (one persistent, graph-captured launch over many detectors) against
+"""Batched plans (graph-captured launches over the work items of many detectors) against
 plain per-detector calls and the oracle, through the C ABI."""
 import sys
 
@@ -105,6 +105,47 @@ def test_batched_forward_equals_plain_and_oracle(B, orc, R):
         ref = orc.totalconv_fwd(L, M, x, truncate_sky(alm_h, LSKY, L), blms[i])
         g = column_gate(outs[0][i].numpy(), ref)
         say(f"  detector {i}: column gate {g:.2e}")
+        assert g <= 1e-11
+
+
+@pytest.mark.parametrize("R", [4, 8])
+def test_batched_forward_shared_walks(B, orc, R):
+    """Detectors with one lmax and one ring set share walks of the recursion (up to four per walk
+    at R 4, two at R 8, largest mbmax first; a member takes a column's row only up to its own
+    mbmax).  Six such detectors with mbmax 9, 6, 4, 4, 2, 0 -- one of them with general complex
+    beam rows, so its walk falls back to one walk per member -- and one detector of another lmax:
+    every output equals the plain call's at the same tile bit for bit and the oracle's to 1e-11."""
+    L, x = 90, S.ring_cosines(2500)                  # 1250 ring pairs: two tiles at R 4
+    spec = [(L, 9, x, "sym"), (L, 6, x, "gen"), (L, 4, x, "sym"), (L, 4, x, "sym"), (L, 2, x, "sym"),
+            (L, 0, x, "sym"), (70, 5, S.ring_cosines(301), "sym")]
+    lsky = 95
+    alm_h = S.sky_alm(lsky, 79)
+    alm = dev(alm_h)
+    dets, blms = [], []
+    for i, (l, m, xr, kind) in enumerate(spec):
+        blm_h = S.beam_blm(l, m, 30.0 + 5 * i, 0.05 * i) if kind == "sym" else S.random_beam(l, m, 500 + i)
+        blms.append(blm_h)
+        dets.append({"lmax": l, "mbmax": m, "cosbeta": xr, "blm": dev(blm_h),
+                     "C": torch.empty((2 * m + 1, l + 1, xr.size), dtype=torch.complex128, device="cuda")})
+    B.set_tile(B.TC_OP_FWD, R)
+    try:
+        say(f"shared-walk forward plan, {len(dets)} detectors, R={R}")
+        plan = B.Plan(B.TC_OP_FWD, dets, lsky, alm)
+        for d in dets:
+            d["C"].fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        plan.close()
+        plains = [B.totalconv_fwd_x(l, m, xr, dev(truncate_sky(alm_h, lsky, l)), d["blm"]).cpu()
+                  for (l, m, xr, _), d in zip(spec, dets)]
+    finally:
+        B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
+    for i, (l, m, xr, kind) in enumerate(spec):
+        got = dets[i]["C"].cpu()
+        assert torch.equal(plains[i], got), f"detector {i} ({kind}, mbmax {m}): batched != plain"
+        ref = orc.totalconv_fwd(l, m, xr, truncate_sky(alm_h, lsky, l), blms[i])
+        g = column_gate(got.numpy(), ref)
+        say(f"  detector {i} (lmax {l}, mbmax {m}, {kind}): column gate {g:.2e}")
         assert g <= 1e-11
 
 
@@ -224,9 +265,9 @@ def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
 
 @pytest.mark.parametrize("first", ["sym", "gen"])
 def test_plan_follows_beams_changed_between_executions(B, first):
-    """Beams edited in place between executions of one plan.  The plan is made with beams whose
-    rows mb and -mb are equal up to a sign (its queue kernel then takes the even / odd form's
-    register budget) or with general complex rows (the general budget), and executed on the two
+    """Beams edited in place between executions of one plan.  The two detectors share a walk; the
+    plan is made with beams whose rows mb and -mb are equal up to a sign (one even / odd walk then
+    feeds both outputs) or with general complex rows (one walk each), and executed on the two
     kinds in turn.  Every execution equals a plain call on the current beams bit for bit."""
     L, M, x = 150, 6, S.ring_cosines(300)
     alm = dev(S.sky_alm(L, 91))
