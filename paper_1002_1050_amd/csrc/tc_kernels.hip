@@ -34,19 +34,20 @@ namespace {
 // longer shapes any kernel: the adjoint's row sums move every step.
 constexpr int TS = 8;         // steps between skip checks
 constexpr int FOLD_EXP = -900;  // fold scaled values into plain doubles at 2^-900
-// A step multiplies max(|d^l|, |d^{l-1}|) by at most 2l+4 < 2^16 for l <= 16384
-// (F0 <= l+1, |x - F1| < 2, F2 <= 2), which bounds growth inside a TS block.
-constexpr int GROWTH_BITS_PER_STEP = 16;
+// A step of the normalised walk (below) multiplies max(|e^l|, |e^{l-1}|) by at most
+// alpha F0 |x - F1| + 1 <= 2 (l+1) 2 + 1 < 2^17 for l <= 16384 (F0 <= l+1, |x - F1| <= 2,
+// alpha <= 2), which bounds growth inside a TS block.
+constexpr int GROWTH_BITS_PER_STEP = 17;
 // Scaled chains are rescaled (and folded) only every RS_STEPS steps: a rescaled chain
-// keeps max(|d|, |d_prev|) < 1, so its significand stays below 2^(16 RS_STEPS) = 2^512
+// keeps max(|e|, |e_prev|) < 1, so its significand stays below 2^(17 RS_STEPS) = 2^544
 // until the next rescale, and a chain still scaled after one (true exponent below -900)
-// stays below 2^-388 until the next, where the skip test of a chain at 2^-100
+// stays below 2^-356 until the next, where the skip test of a chain at 2^-100
 // (GROWTH_BITS_PER_STEP * TS bits of headroom) cannot fire.  Between rescales the skip
 // test looks at the plain chains only.
 constexpr int RS_STEPS = 32;
 template <int TB>
 constexpr int rs_block() { static_assert(TB % TS == 0 && (TB % RS_STEPS == 0 || RS_STEPS % TB == 0), "tile"); return TB < RS_STEPS ? TB : RS_STEPS; }
-constexpr int SKIP_EXP_MAX = -(FOLD_EXP + GROWTH_BITS_PER_STEP * RS_STEPS) - GROWTH_BITS_PER_STEP * TS;  // 260
+constexpr int SKIP_EXP_MAX = -(FOLD_EXP + GROWTH_BITS_PER_STEP * RS_STEPS) - GROWTH_BITS_PER_STEP * TS;  // 220
 static_assert(RS_STEPS % TS == 0 && GROWTH_BITS_PER_STEP * RS_STEPS < 1023 && SKIP_EXP_MAX >= 100,
               "rescale period: no overflow of a scaled significand, no missed hot chain at skip 2^-100");
 
@@ -213,6 +214,62 @@ __device__ __forceinline__ void recursion_coefs(int l, int mb, int ms, int lmax,
     F2 = (l1 * (sqrt(ll * ll - b2) * sqrt(ll * ll - s2))) / (ll * den);
 }
 
+// ------------------------------------------------------------ normalised walk
+// The walks carry e^l = c_l d^l with c_{l0} = c_{l0+1} = 1 and c_{l+1} = c_{l-1} / F2_l.
+// The step then reads e^{l+1} = alpha_l F0 (x - F1) e^l - e^{l-1} with alpha_l = c_{l+1} / c_l:
+// two FP64 instructions, u = fma(x, A', nB') and e' = fma(u, e, -e_prev) with A' = alpha F0 and
+// nB' = -alpha F0 F1, where the plain step takes three.  A value d^l is e^l / c_l: the forward
+// folds 1/c_l into its weights, the adjoint into its per-l sums, the Wigner walk into its stores.
+// Each factor (l+1)^2 - a^2 of F2's denominator exceeds l^2 - a^2 by at least 2l + 1, so
+// F2_l <= (l+1)/l (l/(l+1))^2 = l/(l+1) < 1: c_l >= 1 grows along each parity of l, |d| <= |e|,
+// and every skip test taken on e is conservative.  alpha is largest at its start,
+// q(l0+2)/q(l0+1) <= 2 with q(l)^2 = (l^2 - mb^2)(l^2 - msky^2) / l^2 (the bound the growth
+// constant above assumes; the host tests check it over the extreme columns up to l = 16384).
+struct NormCoef {
+    double A, nB;   // alpha_l F0_l, -alpha_l F0_l F1_l (0 from l = lmax on: the step is off)
+    double ic;      // 1 / c_l
+};
+
+// Coefficients of l = lb + lane for one block of TB values of l, computed by all 64 lanes of
+// one wave (the lanes past TB only take part in the scans).  carry holds c_{lb-2}, c_{lb-1}
+// (ignored for the first block, whose carry is 1, 1) and is replaced by c_{lb+TB-2}, c_{lb+TB-1}.
+// c_l is a product over segments of NORM_SEG values of l, each taking the last two c of the one
+// before, so it rounds the same way for every TB (plans and plain calls agree bit for bit).
+constexpr int NORM_SEG = 32;
+
+template <int TB>
+__device__ __forceinline__ NormCoef norm_coefs(int lb, int l0, int mb, int ms, int lmax, bool first, double* carry)
+{
+    static_assert(TB <= 64 && TB % NORM_SEG == 0, "one wave, whole segments");
+    const int i = threadIdx.x & 63;
+    const int l = lb + i;
+    double A, nB, F2;
+    recursion_coefs(l, mb, ms, lmax, A, nB, F2);
+    double m = 1.0;   // c_l / c_{l-2}
+    if (l >= l0 + 2 && l <= lmax) {
+        double A1, nB1, F2m;
+        recursion_coefs(l - 1, mb, ms, lmax, A1, nB1, F2m);
+        m = 1.0 / F2m;
+    }
+    double c = m;     // products over the lanes of one parity within the segment: offsets 2 .. 16
+    const int j = i & (NORM_SEG - 1);
+#pragma unroll
+    for (int off = 2; off < NORM_SEG; off *= 2) {
+        const double v = __shfl_up(c, off, 64);
+        if (j >= off) c *= v;
+    }
+    if (i < NORM_SEG) c *= (i & 1) ? (first ? 1.0 : carry[1]) : (first ? 1.0 : carry[0]);
+    const double s_even = __shfl(c, NORM_SEG - 2, 64), s_odd = __shfl(c, NORM_SEG - 1, 64);
+    if (i >= NORM_SEG) c *= (i & 1) ? s_odd : s_even;
+    const double c_up = __shfl_up(c, 1, 64);
+    double c_next = __shfl_down(c, 1, 64);                      // c_{l+1}
+    if (i == 63) c_next = (l < lmax) ? (1.0 / F2) * c_up : c_up;  // as the next block's first lane
+    const double alpha = c_next / c;
+    if (i == TB - 2) carry[0] = c;
+    if (i == TB - 1) carry[1] = c;
+    return NormCoef{alpha * A, alpha * nB, 1.0 / c};
+}
+
 // Binary exponent e of max(|d|, |d_prev|) (|v| in [2^(e-1), 2^e)); a zero value does
 // not count (the caller treats d = d_prev = 0 as the zero chain).
 __device__ __forceinline__ int chain_exponent(double d, double dp)
@@ -278,16 +335,13 @@ __device__ __forceinline__ bool check_chain(double& d, double& dp, int& E, int s
     return nz & (te + GROWTH_BITS_PER_STEP * TS > -skip_exp);
 }
 
-// Which l offset of TB block `blk` this lane stages, or -1.  One wave stages a whole
-// block, so that its square roots and divisions keep all lanes busy, and the duty
-// rotates over the workgroup's waves from block to block.
-template <int NT, int TB>
-__device__ __forceinline__ int stage_slot(int tid, int blk)
+// One wave stages a whole block, so that its square roots and divisions keep all lanes busy,
+// and the duty rotates over the workgroup's waves from block to block.
+// Whether this lane's wave stages block `blk` (all of its lanes take part in norm_coefs).
+template <int NT>
+__device__ __forceinline__ bool stage_wave(int tid, int blk)
 {
-    static_assert(TB <= 64, "one wave stages a block");
-    constexpr int NW = NT / 64;
-    const int lane = tid & 63;
-    return ((tid >> 6) == blk % NW && lane < TB) ? lane : -1;
+    return (tid >> 6) == blk % (NT / 64);
 }
 
 __device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
@@ -299,7 +353,8 @@ __device__ __forceinline__ size_t packed_index(int lmax, int l, int m)
 template <int R, int NT, int TB>
 __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
 {
-    __shared__ double4 cf[2][TB];
+    __shared__ double4 cf[2][TB];   // {A', nB', 1/c, -} per l
+    __shared__ double carry[2];
     const int tid = threadIdx.x;
     const int pair = blockIdx.x / a.ntile;
     const int tile = blockIdx.x - pair * a.ntile;
@@ -328,11 +383,10 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
     for (int r = 0; r < R; ++r) scaled |= (E[r] < 0);
     scaled = wave_any(scaled);
 
-    const int st0 = stage_slot<NT, TB>(tid, 0);
-    if (st0 >= 0) {
-        double A, nB, F2;
-        recursion_coefs(l0 + st0, mb, ms, L, A, nB, F2);
-        cf[0][st0] = make_double4(A, nB, F2, 0.0);
+    const int lane = tid & 63;
+    if (stage_wave<NT>(tid, 0)) {
+        const NormCoef k = norm_coefs<TB>(l0, l0, mb, ms, L, true, carry);
+        if (lane < TB) cf[0][lane] = make_double4(k.A, k.nB, k.ic, 0.0);
     }
     __syncthreads();
     const int nblk = (L - l0) / TB + 1;
@@ -357,19 +411,17 @@ __global__ void __launch_bounds__(NT) k_wigner(const WignerArgs a)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (jj[r] >= 0 && l <= L)
-                        out[(size_t)l * a.nring + jj[r]] = (E[r] == 0) ? d[r] : ldexp(d[r], E[r]);
+                        out[(size_t)l * a.nring + jj[r]] = ((E[r] == 0) ? d[r] : ldexp(d[r], E[r])) * k.z;
                     const double u = fma(x[r], k.x, k.y);
-                    const double dn = fma(-k.z, dp[r], u * d[r]);
+                    const double dn = fma(u, d[r], -dp[r]);
                     dp[r] = d[r];
                     d[r] = dn;
                 }
             }
         }
-        const int st = stage_slot<NT, TB>(tid, kb + 1);
-        if (st >= 0 && kb + 1 < nblk) {
-            double A, nB, F2;
-            recursion_coefs(lb + TB + st, mb, ms, L, A, nB, F2);
-            cf[buf ^ 1][st] = make_double4(A, nB, F2, 0.0);
+        if (stage_wave<NT>(tid, kb + 1) && kb + 1 < nblk) {
+            const NormCoef k = norm_coefs<TB>(lb + TB, l0, mb, ms, L, false, carry);
+            if (lane < TB) cf[buf ^ 1][lane] = make_double4(k.A, k.nB, k.ic, 0.0);
         }
         __syncthreads();
     }
@@ -432,15 +484,16 @@ __device__ __forceinline__ double4 output_weights(const RawW (&raw)[NP], int c, 
 template <int NC, bool ROWS>
 constexpr int coef_slots() { return ROWS ? 1 + (NC + 1) / 2 : 1 + NC; }
 
+// The weights take the factor 1/c_l of the normalised walk.
 template <int NC, int NP>
-__device__ __forceinline__ void stage_block(const FwdArgs& a, const RawW (&raw)[NP], int l, int mb, int ms,
-                                            double4* slot)
+__device__ __forceinline__ void stage_block(const NormCoef& k, const RawW (&raw)[NP], int l, int ms, double4* slot)
 {
-    double A, nB, F2;
-    recursion_coefs(l, mb, ms, a.lmax, A, nB, F2);
-    slot[0] = make_double4(A, nB, F2, 0.0);
+    slot[0] = make_double4(k.A, k.nB, 0.0, 0.0);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) slot[1 + c] = output_weights<NC, NP>(raw, c, l, ms);
+    for (int c = 0; c < NC; ++c) {
+        const double4 w = output_weights<NC, NP>(raw, c, l, ms);
+        slot[1 + c] = make_double4(w.x * k.ic, w.y * k.ic, w.z * k.ic, w.w * k.ic);
+    }
 }
 
 // The even / odd form needs w1 only: b^c_{l,mb} of each output and the sky, which the
@@ -472,17 +525,14 @@ __device__ __forceinline__ RawRows<NC> load_rows_raw(const FwdArgs& a, int l, in
 }
 
 template <int NC>
-__device__ __forceinline__ void stage_block_rows(const FwdArgs& a, const RawRows<NC>& w, int l, int mb, int ms,
-                                                 double4* slot)
+__device__ __forceinline__ void stage_block_rows(const NormCoef& k, const RawRows<NC>& w, double4* slot)
 {
-    double A, nB, F2;
-    recursion_coefs(l, mb, ms, a.lmax, A, nB, F2);
-    slot[0] = make_double4(A, nB, F2, 0.0);
+    slot[0] = make_double4(k.A, k.nB, 0.0, 0.0);
     double wr[NC + 1], wi[NC + 1];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {   // conj(b) * s, as in pair_weights
-        wr[c] = w.br[c] * w.sr + w.bi[c] * w.si;
-        wi[c] = w.br[c] * w.si - w.bi[c] * w.sr;
+    for (int c = 0; c < NC; ++c) {   // conj(b) * s, as in pair_weights, times 1/c_l
+        wr[c] = (w.br[c] * w.sr + w.bi[c] * w.si) * k.ic;
+        wi[c] = (w.br[c] * w.si - w.bi[c] * w.sr) * k.ic;
     }
     wr[NC] = 0.0; wi[NC] = 0.0;
 #pragma unroll
@@ -514,7 +564,7 @@ __device__ __forceinline__ void fwd_steps(const double4 (*cf)[NS], int s0,
                 }
             }
             const double u = fma(x[r], k.x, k.y);
-            const double dn = fma(-k.z, dp[r], u * d[r]);
+            const double dn = fma(u, d[r], -dp[r]);
             dp[r] = d[r];
             d[r] = dn;
         }
@@ -560,19 +610,24 @@ __device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[NS], int s0,
                 }
             }
             const double u = fma(x[r], k.x, k.y);
-            const double dn = fma(-k.z, dp[r], u * d[r]);
+            const double dn = fma(u, d[r], -dp[r]);
             dp[r] = d[r];
             d[r] = dn;
         }
     }
 }
 
+template <int TB, int NS>
+struct FwdShared {
+    double4 cf[2][TB][NS];   // coefficient slots of the current and the next block
+    double carry[2];         // c of the last two l of the latest staged block
+};
+
 // One (column, ring tile) work item of the forward over pairs P0 .. P0 + NP - 1 into outputs
 // P0 .. P0 + NC - 1.  ROWS: the even / odd form, output c with beam row sign rows_sign[c].
-// cf holds the coefficient slots of the current and the next block.
 template <int R, int NT, int TB, int NC, int NP, bool ROWS, int P0, int NS>
 __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int tile, const int* rows_sign,
-                                                double4 (&cf)[2][TB][NS])
+                                                FwdShared<TB, NS>& sh_)
 {
     static_assert(NC == 1 || NC == NP, "one output per pair, or one summed output");
     static_assert(!ROWS || NC == NP, "the even / odd form: one output per pair");
@@ -620,16 +675,20 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
             for (int p = 0; p < NP; ++p) raw[p] = load_weights_raw(a, P0 + p, l, mb, ms);
         }
     };
-    auto stage_raw = [&](int l, double4* slot) {
-        if constexpr (ROWS)
-            stage_block_rows<NC>(a, rraw, l, mb, ms, slot);
-        else
-            stage_block<NC, NP>(a, raw, l, mb, ms, slot);
+    // the staging wave's lanes: l = lb + lane; the coefficients need all 64 lanes
+    const int lane = tid & 63;
+    auto stage_raw = [&](int lb, bool first, double4 (*slots)[NS]) {
+        const NormCoef k = norm_coefs<TB>(lb, l0, mb, ms, L, first, sh_.carry);
+        if (lane < TB) {
+            if constexpr (ROWS)
+                stage_block_rows<NC>(k, rraw, slots[lane]);
+            else
+                stage_block<NC, NP>(k, raw, lb + lane, ms, slots[lane]);
+        }
     };
-    const int st0 = stage_slot<NT, TB>(tid, 0);
-    if (st0 >= 0) {
-        load_raw(l0 + st0);
-        stage_raw(l0 + st0, cf[0][st0]);
+    if (stage_wave<NT>(tid, 0)) {
+        if (lane < TB) load_raw(l0 + lane);
+        stage_raw(l0, true, sh_.cf[0]);
     }
     __syncthreads();
     constexpr int RS_BLK = rs_block<TB>();   // steps between rescales of scaled chains
@@ -637,9 +696,8 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
     for (int kb = 0; kb < nblk; ++kb) {
         const int buf = kb & 1;
         const int lb = l0 + kb * TB;
-        const int st = stage_slot<NT, TB>(tid, kb + 1);
-        const bool stage = (st >= 0) && (kb + 1 < nblk);
-        if (stage) load_raw(lb + TB + st);   // in flight during the block
+        const bool stage = stage_wave<NT>(tid, kb + 1) && (kb + 1 < nblk);
+        if (stage && lane < TB) load_raw(lb + TB + lane);   // in flight during the block
         for (int s1 = 0; s1 < TB; s1 += RS_BLK) {
             if (scaled) {
                 bool any = false;
@@ -664,14 +722,14 @@ __device__ __forceinline__ void fwd_column_walk(const FwdArgs& a, int ci, int ti
                 if (!acc_on)
                     acc_on = wave_any(scaled ? lane_may_be_hot_plain<R>(d, dp, E, thr) : lane_may_be_hot<R>(d, dp, thr));
                 if (!acc_on)
-                    fwd_steps<R, NC, false>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                    fwd_steps<R, NC, false>(sh_.cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
                 else if constexpr (ROWS)
-                    fwd_steps_rows<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                    fwd_steps_rows<R, NC, true>(sh_.cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
                 else
-                    fwd_steps<R, NC, true>(cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
+                    fwd_steps<R, NC, true>(sh_.cf[buf], s0, x, d, dp, c1r, c1i, c2r, c2i);
             }
         }
-        if (stage) stage_raw(lb + TB + st, cf[buf ^ 1][st]);
+        if (stage) stage_raw(lb + TB, false, sh_.cf[buf ^ 1]);
         __syncthreads();
     }
 
@@ -719,23 +777,23 @@ __device__ __forceinline__ int row_sign(const FwdArgs& a, int p, int mb)
 template <int R, int NT, int TB, int NC, int NP>
 __global__ void __launch_bounds__(NT, (fwd_min_waves<R, NC, NP>())) k_fwd(const FwdArgs a)
 {
-    __shared__ double4 cf[2][TB][1 + NC];
+    __shared__ FwdShared<TB, 1 + NC> sh;
     const int ci = blockIdx.x / a.ntile;
     if constexpr (NC == 1 && NP == 1) {
         if (a.beam_sym[0] && row_sign(a, 0, ldg(a.col.mb + ci)) != 0) return;
     }
     const int none[NC] = {};
-    fwd_column_walk<R, NT, TB, NC, NP, false, 0>(a, ci, blockIdx.x - ci * a.ntile, none, cf);
+    fwd_column_walk<R, NT, TB, NC, NP, false, 0>(a, ci, blockIdx.x - ci * a.ntile, none, sh);
 }
 
 template <int R, int NT, int TB>
 __global__ void __launch_bounds__(NT, (rows_min_waves<R>())) k_fwd_rows(const FwdArgs a)
 {
-    __shared__ double4 cf[2][TB][2];
+    __shared__ FwdShared<TB, 2> sh;
     const int ci = blockIdx.x / a.ntile;
     const int s[1] = {row_sign(a, 0, ldg(a.col.mb + ci))};
     if (s[0] == 0) return;
-    fwd_column_walk<R, NT, TB, 1, 1, true, 0>(a, ci, blockIdx.x - ci * a.ntile, s, cf);
+    fwd_column_walk<R, NT, TB, 1, 1, true, 0>(a, ci, blockIdx.x - ci * a.ntile, s, sh);
 }
 
 // Batched form: one workgroup per (walk, column, ring tile) item, the items in order of cost,
@@ -755,7 +813,7 @@ constexpr int items_min_waves() { return R >= 4 ? 2 : 3; }
 
 template <int R, int NT, int TB, int NS, int P>
 __device__ __forceinline__ void fwd_item_alone(const FwdArgs& a, int ci, int tile, int k, const int (&s)[kMaxPairs],
-                                               double4 (&cf)[2][TB][NS])
+                                               FwdShared<TB, NS>& cf)
 {
     if (P < k) {
         if (s[P] != 0)
@@ -772,7 +830,7 @@ __global__ void __launch_bounds__(NT, (items_min_waves<R>())) k_fwd_items(const 
     constexpr int K = walk_pairs<R>();
     static_assert(K == 2 || K == 4, "walk sizes");
     constexpr int NS = coef_slots<K, true>() > 2 ? coef_slots<K, true>() : 2;
-    __shared__ double4 cf[2][TB][NS];
+    __shared__ FwdShared<TB, NS> cf;
     const int* item = items + 3 * (size_t)blockIdx.x;
     const FwdArgs a = walks[item[0]];
     const int ci = item[1], tile = item[2];
@@ -842,9 +900,10 @@ constexpr int out_stride() { return (NT / 64) * 4 * 4 + 1; }
 // slots behind its end, so that the TS consecutive offsets of a step group never wrap.
 template <int NT, int TB>
 struct AdjShared {
-    double2 cfa[4 * TB + TS];                     // {A, nB} per l offset, slot = offset mod 4 TB
-    double cff[4 * TB + TS];                      // F2 per l offset
+    double2 cfa[4 * TB + TS];                     // {A', nB'} per l offset, slot = offset mod 4 TB
+    double cic[4 * TB + TS];                      // 1 / c_l per l offset (the copy is not read)
     double out[2 * TB * out_stride<NT>()];        // emitted row sums
+    double carry[2];                              // normalisation carry between blocks
 };
 
 template <int NT, int TB>
@@ -919,16 +978,13 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     const size_t urow = packed_index(L, 0, ms);   // + l
 
     auto stage = [&](int blk) {
-        const int st = stage_slot<NT, TB>(tid, blk);
-        if (st >= 0) {
-            double A, nB, F2;
-            recursion_coefs(l0 + blk * TB + st, mb, ms, L, A, nB, F2);
-            const int slot = (blk * TB + st) & CF_MASK;
-            sh_.cfa[slot] = make_double2(A, nB);
-            sh_.cff[slot] = F2;
-            if (slot < TS) {   // the copy behind the ring's end
-                sh_.cfa[CF_N + slot] = make_double2(A, nB);
-                sh_.cff[CF_N + slot] = F2;
+        if (stage_wave<NT>(tid, blk)) {
+            const NormCoef k = norm_coefs<TB>(l0 + blk * TB, l0, mb, ms, L, blk == 0, sh_.carry);
+            if (lane < TB) {
+                const int slot = (blk * TB + lane) & CF_MASK;
+                sh_.cfa[slot] = make_double2(k.A, k.nB);
+                sh_.cic[slot] = k.ic;
+                if (slot < TS) sh_.cfa[CF_N + slot] = make_double2(k.A, k.nB);   // the copy behind the ring's end
             }
         }
     };
@@ -953,8 +1009,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     auto shift_b_to_a = [&]() {
         a0 = row_shift_up(b0); a1 = row_shift_up(b1); a2 = row_shift_up(b2); a3 = row_shift_up(b3);
     };
-    // one step of the R chains of this lane: coefficients k, f2; the sums s0..s3 take d * Cbar
-    auto step = [&](const double2 k, const double f2, double& s0, double& s1, double& s2, double& s3) {
+    // one step of the R chains of this lane: coefficients k; the sums s0..s3 take e * Cbar
+    auto step = [&](const double2 k, double& s0, double& s1, double& s2, double& s3) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             s0 = fma(d[r], g1r[r], s0);
@@ -962,7 +1018,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
             s2 = fma(d[r], g2r[r], s2);
             s3 = fma(d[r], g2i[r], s3);
             const double u = fma(x[r], k.x, k.y);
-            const double dn = fma(-f2, dp[r], u * d[r]);
+            const double dn = fma(u, d[r], -dp[r]);
             dp[r] = d[r];
             d[r] = dn;
         }
@@ -1001,7 +1057,6 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                         const bool live = tt >= kr;
                         const int off = live ? tt - kr : 0;
                         const double2 k = sh_.cfa[off & CF_MASK];
-                        const double f2 = sh_.cff[off & CF_MASK];
                         if (t & 1) shift_b_to_a(); else shift_a_to_b();
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
@@ -1014,7 +1069,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                                 b2 = fma(dd, g2r[r], b2); b3 = fma(dd, g2i[r], b3);
                             }
                             const double u = fma(x[r], k.x, k.y);
-                            const double dn = fma(-f2, dp[r], u * d[r]);
+                            const double dn = fma(u, d[r], -dp[r]);
                             dp[r] = live ? d[r] : dp[r];
                             d[r] = live ? dn : d[r];
                         }
@@ -1024,19 +1079,16 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                     // pairs of steps; each pair's coefficients are read during the pair before
                     const int cb = (t0 - kr) & CF_MASK;
                     double2 kn0 = sh_.cfa[cb], kn1 = sh_.cfa[cb + 1];
-                    double fn0 = sh_.cff[cb], fn1 = sh_.cff[cb + 1];
 #pragma unroll
                     for (int h = 0; h < TS; h += 2) {
                         const double2 k0 = kn0, k1 = kn1;
-                        const double f0 = fn0, f1 = fn1;
                         if (h + 2 < TS) {
                             kn0 = sh_.cfa[cb + h + 2]; kn1 = sh_.cfa[cb + h + 3];
-                            fn0 = sh_.cff[cb + h + 2]; fn1 = sh_.cff[cb + h + 3];
                         }
                         shift_a_to_b();
-                        step(k0, f0, b0, b1, b2, b3);
+                        step(k0, b0, b1, b2, b3);
                         shift_b_to_a();
-                        step(k1, f1, a0, a1, a2, a3);
+                        step(k1, a0, a1, a2, a3);
                         emit2(t0 + h);
                     }
                 } else {
@@ -1044,11 +1096,10 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
 #pragma unroll
                     for (int t = 0; t < TS; ++t) {
                         const double2 k = sh_.cfa[cb + t];
-                        const double f2 = sh_.cff[cb + t];
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const double u = fma(x[r], k.x, k.y);
-                            const double dn = fma(-f2, dp[r], u * d[r]);
+                            const double dn = fma(u, d[r], -dp[r]);
                             dp[r] = d[r];
                             d[r] = dn;
                         }
@@ -1071,6 +1122,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 double v = 0.0;
 #pragma unroll
                 for (int w = 0; w < NW * 4; ++w) v += src[4 * w];
+                v *= sh_.cic[o & CF_MASK];   // e^l back to d^l
                 double* dst = reinterpret_cast<double*>(c < 2 ? U : V) + 2 * (urow + l0 + o) + (c & 1);
                 stg(dst, (tile == 0) ? v : ldg(dst) + v);
             }
