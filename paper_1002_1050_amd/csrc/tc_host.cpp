@@ -516,12 +516,8 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
             need |= (alm_bar && alm_bar[p]) || (blm_bar && blm_bar[p]);
         if (!need) continue;
         a.Cbar = Cbar[k];
-        // one launch per ring tile, in order: tile 0 writes each column's U and V, later tiles add
-        rc = timed_launch(TC_OP_ADJ, stream, [&] {
-            for (a.tile = 0; a.tile < L.ntile; ++a.tile)
-                if (int r = tc::launch_adj(a, t, stream)) return r;
-            return 0;
-        });
+        // one workgroup per column walks its ring tiles in order: tile 0 writes U and V, later tiles add
+        rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
         if (rc) return hip_fail(rc, "totalconv_adj launch");
         for (int p = p0; p < p1; ++p) {
             tc::EpiArgs e{};
@@ -1016,8 +1012,8 @@ int fwd_noalloc(int lmax, int mbmax, int nring, const double* beta, const double
 // records, the work items sorted by cost (longest first) and, for the adjoint, the partial
 // sums.  Forward walks are groups of up to kMaxPairs detectors that share lmax and rings (one
 // recursion feeds each member's output); every adjoint detector walks alone.  The plan's graph
-// is: [beam row signs ->] one launch over the items (the adjoint: one per ring-tile round)
-// [-> sky-gradient epilogue over all detectors -> per-detector beam-gradient epilogues].
+// is: [beam row signs ->] one launch over the items [-> sky-gradient epilogue over all
+// detectors -> per-detector beam-gradient epilogues].
 
 struct tc_plan_s {
     int op = 0;
@@ -1077,11 +1073,26 @@ int check_detector(int i, const tc_detector& d, int op, int lmax_sky)
     return TC_OK;
 }
 
+// R of a walk over nslot ring slots: the plan's R, halved while half of it still covers every
+// slot in one ring tile (the lanes of a workgroup that hold no ring would walk for nothing).
+int walk_R(const tc::Tile& t, int nslot)
+{
+    int R = t.R;
+    while (R > 2 && t.NT * (R / 2) >= nslot) R /= 2;
+    return R;
+}
+
+struct Walk {
+    std::vector<int> mem;   // detectors, largest mbmax first
+    tc::Tile tile;          // the plan's tile with the walk's R
+};
+
 // Walks of a plan: detectors with the same lmax and the same ring cosines (bit for bit) form
-// one class; each class, ordered by mbmax (largest first, then by index), is cut into walks of
-// at most `per_walk` detectors.  Walks come in the order of their first detector.
-std::vector<std::vector<int>> group_detectors(int ndet, const tc_detector* dets,
-                                              const std::vector<std::vector<double>>& xr, int per_walk)
+// one class, whose walks take the class's R; each class, ordered by mbmax (largest first, then
+// by index), is cut into walks of as many detectors as a forward walk at that R serves (one for
+// the adjoint).  Walks come in the order of their first detector.
+std::vector<Walk> group_detectors(int op, int ndet, const tc_detector* dets,
+                                  const std::vector<std::vector<double>>& xr, const tc::Tile& t)
 {
     std::vector<std::vector<int>> cls;
     for (int i = 0; i < ndet; ++i) {
@@ -1096,11 +1107,14 @@ std::vector<std::vector<int>> group_detectors(int ndet, const tc_detector* dets,
         }
         if (!placed) cls.push_back({i});
     }
-    std::vector<std::vector<int>> walks;
+    std::vector<Walk> walks;
     for (auto& c : cls) {
         std::stable_sort(c.begin(), c.end(), [&](int a, int b) { return dets[a].mbmax > dets[b].mbmax; });
-        for (size_t k = 0; k < c.size(); k += (size_t)per_walk)
-            walks.emplace_back(c.begin() + k, c.begin() + std::min(c.size(), k + (size_t)per_walk));
+        tc::Tile wt = t;
+        wt.R = walk_R(t, count_slots(dets[c[0]].nring, xr[c[0]].data()));
+        const size_t per_walk = op == TC_OP_FWD ? (size_t)tc::fwd_walk_pairs(wt) : 1;
+        for (size_t k = 0; k < c.size(); k += per_walk)
+            walks.push_back({std::vector<int>(c.begin() + k, c.begin() + std::min(c.size(), k + per_walk)), wt});
     }
     return walks;
 }
@@ -1125,9 +1139,8 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         if (int rc = check_detector(i, dets[i], op, lmax_sky)) return rc;
         if (int rc = detector_rings(i, dets[i], xr[i])) return rc;
     }
-    const tc::Tile tile = default_tile(op, 1 << 20);   // the batched kernel serves every lmax with one R
-    const std::vector<std::vector<int>> walks =
-        group_detectors(ndet, dets, xr, op == TC_OP_FWD ? tc::fwd_walk_pairs(tile) : 1);
+    const tc::Tile tile = default_tile(op, 1 << 20);   // the largest R of the plan's walks
+    const std::vector<Walk> walks = group_detectors(op, ndet, dets, xr, tile);
     const int nwalk = (int)walks.size();
 
     tc_plan_s* p = new tc_plan_s;
@@ -1144,8 +1157,8 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     size_t off = 0;
     long long nitems = 0;
     for (int w = 0; w < nwalk; ++w) {
-        const tc_detector& d = dets[walks[w][0]];
-        lay[w] = make_layout(op, d.lmax, d.mbmax, d.nring, xr[walks[w][0]].data(), p->tile);
+        const tc_detector& d = dets[walks[w].mem[0]];
+        lay[w] = make_layout(op, d.lmax, d.mbmax, d.nring, xr[walks[w].mem[0]].data(), walks[w].tile);
         base[w] = off;
         off = align_up(off + lay[w].total);
         nitems += (long long)lay[w].ncol * lay[w].ntile;
@@ -1163,7 +1176,6 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     const size_t items_off = off;
     off = align_up(off + sizeof(int) * 3 * (size_t)nitems);
     p->dbytes = off;
-    p->nitems = (int)nitems;
     int rc = (int)hipMalloc(&p->dmem, p->dbytes);
     if (rc) {
         (void)hipGetLastError();   // the failed allocation must not be reported by the next launch check
@@ -1176,11 +1188,12 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     std::vector<tc::FwdArgs> fa(op == TC_OP_FWD ? nwalk : 0);
     std::vector<tc::AdjArgs> aa(op == TC_OP_ADJ ? nwalk : 0);
     std::vector<tc::EpiArgs> ea(ndet);
-    struct Item { int walk, col, tile; long long cost; };
+    struct Item { int R, walk, col, tile; long long cost; };
     std::vector<Item> items;
     items.reserve((size_t)nitems);
     for (int w = 0; w < nwalk; ++w) {
-        const std::vector<int>& mem = walks[w];
+        const std::vector<int>& mem = walks[w].mem;
+        const tc::Tile& wt = walks[w].tile;
         const tc_detector& d = dets[mem[0]];
         const Layout& L = lay[w];
         std::vector<char> img(L.tables_end, 0);
@@ -1194,12 +1207,16 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         const int* cmb = reinterpret_cast<const int*>(img.data() + L.colmb);
         for (int c = 0; c < L.ncol; ++c) {
             const int len = d.lmax - std::max(std::abs(cmb[c]), cms[c]) + 1;
+            if (op == TC_OP_ADJ) {   // one item walks every ring tile of the column
+                items.push_back({wt.R, w, c, 0, (long long)len * L.nslot});
+                continue;
+            }
             int k = 0;   // members with this column's beam row
             for (int i : mem) k += dets[i].mbmax >= std::abs(cmb[c]);
             for (int t = 0; t < L.ntile; ++t) {
-                const int slots = std::min(p->tile.NT * p->tile.R, L.nslot - t * p->tile.NT * p->tile.R);
-                // a step costs about 3 + 2k operations per chain (the recursion, k outputs' sums)
-                items.push_back({w, c, t, (long long)len * slots * (3 + 2 * k)});
+                const int slots = std::min(wt.NT * wt.R, L.nslot - t * wt.NT * wt.R);
+                // a step costs about 2 + 2k operations per chain (the recursion, k outputs' sums)
+                items.push_back({wt.R, w, c, t, (long long)len * slots * (2 + 2 * k)});
             }
         }
         if (op == TC_OP_FWD) {
@@ -1234,21 +1251,28 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             e.U = a.U; e.V = a.V; e.alm = alm; e.blm = d.blm; e.alm_bar = nullptr; e.blm_bar = d.blm_bar;
         }
     }
-    // forward: one launch, longest first.  Adjoint: one round per ring tile index, in order (tile 0
-    // writes each column's U and V, a later tile adds to them), each round longest first.
-    std::stable_sort(items.begin(), items.end(), [op](const Item& a, const Item& b) {
-        if (op == TC_OP_ADJ && a.tile != b.tile) return a.tile < b.tile;
-        return a.cost > b.cost;
+    // one launch per R, over its items longest first
+    p->nitems = (int)items.size();
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+        return a.R != b.R ? a.R > b.R : a.cost > b.cost;
     });
-    std::vector<int> round_start(1, 0);   // item ranges of the rounds
-    for (size_t k = 1; k < items.size(); ++k)
-        if (op == TC_OP_ADJ && items[k].tile != items[k - 1].tile) round_start.push_back((int)k);
-    round_start.push_back((int)items.size());
-    std::vector<int> it3(3 * items.size());
+    struct Launch { tc::Tile tile; int first, n; long long cost; };
+    std::vector<Launch> launches;
     for (size_t k = 0; k < items.size(); ++k) {
-        it3[3 * k] = items[k].walk;
-        it3[3 * k + 1] = items[k].col;
-        it3[3 * k + 2] = items[k].tile;
+        if (launches.empty() || launches.back().tile.R != items[k].R) {
+            tc::Tile lt = tile;
+            lt.R = items[k].R;
+            launches.push_back({lt, (int)k, 0, 0});
+        }
+        launches.back().n += 1;
+        launches.back().cost += items[k].cost;
+    }
+    const int per_item = op == TC_OP_FWD ? 3 : 2;
+    std::vector<int> it3((size_t)per_item * items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        it3[per_item * k] = items[k].walk;
+        it3[per_item * k + 1] = items[k].col;
+        if (per_item == 3) it3[per_item * k + 2] = items[k].tile;
     }
     rc = (int)hipMemcpy(dm + args_off, op == TC_OP_FWD ? (const void*)fa.data() : (const void*)aa.data(), args_bytes,
                         hipMemcpyHostToDevice);
@@ -1257,23 +1281,49 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     if (!rc) rc = (int)hipMemcpy(dm + items_off, it3.data(), sizeof(int) * it3.size(), hipMemcpyHostToDevice);
     if (rc) { destroy_plan(p); return hip_fail(rc, "plan: argument upload"); }
 
-    // ---- capture the graph on a private stream (the caller's stream may be the legacy one)
+    // ---- capture the graph on a private stream (the caller's stream may be the legacy one).  The
+    // launches of the different R run side by side: the costliest on the capture stream, each other
+    // on a stream of its own forked from it and joined back before the epilogues.
+    const int nside = launches.empty() ? 0 : (int)launches.size() - 1;
+    std::vector<hipStream_t> side(nside, nullptr);
+    std::vector<hipEvent_t> joins(nside, nullptr);
+    hipEvent_t fork = nullptr;
     hipStream_t cs = nullptr;
+    auto release_capture = [&] {
+        for (hipStream_t q : side) if (q) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : joins) if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        if (cs) (void)hipStreamDestroy(cs);
+    };
     rc = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (rc) { destroy_plan(p); return hip_fail(rc, "plan: capture stream"); }
+    if (!rc) rc = (int)hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (int k = 0; k < nside && !rc; ++k) {
+        rc = (int)hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+        if (!rc) rc = (int)hipEventCreateWithFlags(&joins[k], hipEventDisableTiming);
+    }
+    if (rc) { release_capture(); destroy_plan(p); return hip_fail(rc, "plan: capture streams"); }
+    std::stable_sort(launches.begin(), launches.end(), [](const Launch& a, const Launch& b) { return a.cost > b.cost; });
     rc = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int* d_items = reinterpret_cast<const int*>(dm + items_off);
     for (int i = 0; i < ndet && !rc && op == TC_OP_FWD; ++i)   // beam row signs, on every execution
         rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, reinterpret_cast<int*>(dm + sym_off[i]),
                                       cs);
-    if (!rc && op == TC_OP_FWD)
-        rc = tc::launch_fwd_items(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items, p->nitems, p->tile, cs);
+    if (!rc && nside > 0) rc = (int)hipEventRecord(fork, cs);
+    for (size_t k = 0; k < launches.size() && !rc; ++k) {
+        hipStream_t q = k == 0 ? cs : side[k - 1];
+        if (k > 0) rc = (int)hipStreamWaitEvent(q, fork, 0);
+        const Launch& l = launches[k];
+        if (!rc && op == TC_OP_FWD)
+            rc = tc::launch_fwd_items(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items + 3 * (size_t)l.first,
+                                      l.n, l.tile, q);
+        if (!rc && op == TC_OP_ADJ)
+            rc = tc::launch_adj_items(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items + 2 * (size_t)l.first,
+                                      l.n, l.tile, q);
+        if (!rc && k > 0) rc = (int)hipEventRecord(joins[k - 1], q);
+    }
+    for (int k = 0; k < nside && !rc; ++k) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
     if (!rc && op == TC_OP_ADJ) {
-        for (size_t r = 0; r + 1 < round_start.size() && !rc; ++r)
-            rc = tc::launch_adj_items(reinterpret_cast<const tc::AdjArgs*>(dm + args_off),
-                                      d_items + 3 * (size_t)round_start[r], round_start[r + 1] - round_start[r],
-                                      p->tile, cs);
-        if (!rc && alm_bar)
+        if (alm_bar)
             rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
                                           cs);
         for (int i = 0; i < ndet && !rc; ++i)
@@ -1281,7 +1331,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     }
     hipGraph_t g = nullptr;
     const int rc_end = (int)hipStreamEndCapture(cs, &g);
-    (void)hipStreamDestroy(cs);
+    release_capture();
     p->graph = g;
     if (rc || rc_end) { destroy_plan(p); return hip_fail(rc ? rc : rc_end, "plan: graph capture"); }
     rc = (int)hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);

@@ -65,7 +65,6 @@ struct FwdArgs {
 
 struct AdjArgs {
     int lmax, mbmax, nring, nslot, ncol, ntile;
-    int tile;              // plain launch: the ring tile it walks (tile 0 writes U, V; later tiles add)
     int skip_exp;
     RingTables ring;
     const int* slots;
@@ -122,7 +121,8 @@ int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void*
 int launch_adj(const AdjArgs& a, Tile t, void* stream);
 int launch_adj_epilogue(const EpiArgs& e, void* stream);
 
-// Batched launches: one workgroup per item, items = (walk or detector, column, tile) triples.
+// Batched launches: one workgroup per item; forward items are (walk, column, ring tile) triples,
+// adjoint items (detector, column) pairs (the workgroup walks every ring tile of the column).
 int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t, void* stream);
 // Detectors one batched forward walk serves with tile t (at most kMaxPairs).
 int fwd_walk_pairs(Tile t);

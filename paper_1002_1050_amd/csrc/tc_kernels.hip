@@ -971,8 +971,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     bool acc_on = (a.skip_exp <= 0);    // wave-uniform
     const double thr = hot_threshold(a.skip_exp);
 
-    // one U and one V row per column: ring tile 0 writes them, each later tile (a later launch,
-    // or a later round of the batched plan) adds to them
+    // one U and one V row per column: ring tile 0 writes them, each later tile (walked after it
+    // by the same workgroup) adds to them
     double2* U = reinterpret_cast<double2*>(a.U) + (size_t)(mb + a.mbmax) * (size_t)a.P;
     double2* V = reinterpret_cast<double2*>(a.V) + (size_t)(mb + a.mbmax) * (size_t)a.P;
     const size_t urow = packed_index(L, 0, ms);   // + l
@@ -1130,24 +1130,36 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     }
 }
 
+// All ring tiles of column ci, one after the other in one workgroup: tile 0 writes the
+// column's U and V rows, each later tile adds to them (the same thread writes an element in
+// every tile), so no launch has to wait for another.  The column's values the compiler keeps
+// across tiles spill outside the step loops only.
+template <int R, int NT, int TB, int TR>
+__device__ __forceinline__ void adj_tiles(const AdjArgs& a, int ci, AdjShared<NT, TB>& sh)
+{
+    for (int tile = 0; tile < a.ntile; ++tile) {
+        if (tile > 0) __syncthreads();   // the tile before still reads the LDS ring in its last block sums
+        adj_column<R, NT, TB, TR>(a, ci, tile, sh);
+    }
+}
+
 template <int R, int NT, int TB, int TR>
 __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjArgs a)
 {
     static_assert(adj_lds_bytes<NT, TB>() * adj_min_waves<R, TB>() <= 160 * 1024, "LDS per CU");
     __shared__ AdjShared<NT, TB> sh;
-    adj_column<R, NT, TB, TR>(a, blockIdx.x, a.tile, sh);
+    adj_tiles<R, NT, TB, TR>(a, blockIdx.x, sh);
 }
 
-// Batched form: one workgroup per (detector, column, ring tile) item of one ring-tile round,
-// the items longest first.
+// Batched form: one workgroup per (detector, column) item, the items longest first.
 template <int R, int NT, int TB, int TR>
 __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_items(const AdjArgs* __restrict__ dets,
                                                                             const int* __restrict__ items)
 {
     __shared__ AdjShared<NT, TB> sh;
-    const int* item = items + 3 * (size_t)blockIdx.x;
+    const int* item = items + 2 * (size_t)blockIdx.x;
     const AdjArgs a = dets[item[0]];
-    adj_column<R, NT, TB, TR>(a, item[1], item[2], sh);
+    adj_tiles<R, NT, TB, TR>(a, item[1], sh);
 }
 
 // u(mb, ms, l) = U[mb] + (-1)^(l-ms) V[-mb], defined for l >= max(|mb|, ms)
@@ -1320,7 +1332,7 @@ int launch_fwd(const FwdArgs& a, Tile t, void* stream)
 
 int launch_adj(const AdjArgs& a, Tile t, void* stream)
 {
-    const int blocks = a.ncol;   // ring tile a.tile of every column
+    const int blocks = a.ncol;   // every ring tile of a column in one workgroup
 #define X(r, tb, tr) \
     if (t.R == r && t.TB == tb && t.TR == tr) return launch_grid(k_adj<r, 256, tb, tr>, a, blocks, 256, stream);
     TC_ADJ_VARIANTS(X)

@@ -56,6 +56,28 @@ DETS = [  # lmax, mbmax, ring cosines
 LSKY = 310
 
 
+def count_slots(x):
+    """Ring slots of a ring set: mirror pairs (x_j, x_{n-1-j} = -x_j) and single rings."""
+    n, k = x.size, 0
+    for j in range(n):
+        jp = n - 1 - j
+        if j < jp and x[jp] == -x[j]:
+            k += 1
+        elif j > jp and x[j] == -x[jp]:
+            continue
+        else:
+            k += 1
+    return k
+
+
+def walk_R(R, x, NT=256):
+    """The R a plan walks a detector with at plan R: halved while half still covers its slots."""
+    n = count_slots(x)
+    while R > 2 and NT * (R // 2) >= n:
+        R //= 2
+    return R
+
+
 def column_gate(got, ref):
     got = got.reshape(-1, got.shape[-1])
     ref = ref.reshape(-1, ref.shape[-1])
@@ -76,7 +98,8 @@ def test_batched_forward_equals_plain_and_oracle(B, orc, R):
         dets.append({"lmax": L, "mbmax": M, "cosbeta": x, "blm": dev(blm_h),
                      "C": torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda")})
     # plan and plain calls at one tile: which terms below the skip level a wavefront sums
-    # depends on which chains share it, so bitwise equality holds tile for tile
+    # depends on which chains share it, so bitwise equality holds tile for tile (the plan walks a
+    # detector whose rings fill a smaller tile at a smaller R)
     B.set_tile(B.TC_OP_FWD, R)
     try:
         say(f"batched forward plan, {len(dets)} detectors, R={R}")
@@ -96,6 +119,7 @@ def test_batched_forward_equals_plain_and_oracle(B, orc, R):
         plains = []
         for i, (L, M, x) in enumerate(DETS):
             a_d = dev(truncate_sky(alm_h, LSKY, L))
+            B.set_tile(B.TC_OP_FWD, walk_R(R, x))
             plains.append(B.totalconv_fwd_x(L, M, x, a_d, dets[i]["blm"]).cpu())
     finally:
         B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
@@ -136,8 +160,10 @@ def test_batched_forward_shared_walks(B, orc, R):
         plan.execute()
         torch.cuda.synchronize()
         plan.close()
-        plains = [B.totalconv_fwd_x(l, m, xr, dev(truncate_sky(alm_h, lsky, l)), d["blm"]).cpu()
-                  for (l, m, xr, _), d in zip(spec, dets)]
+        plains = []
+        for (l, m, xr, _), d in zip(spec, dets):
+            B.set_tile(B.TC_OP_FWD, walk_R(R, xr))
+            plains.append(B.totalconv_fwd_x(l, m, xr, dev(truncate_sky(alm_h, lsky, l)), d["blm"]).cpu())
     finally:
         B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     for i, (l, m, xr, kind) in enumerate(spec):
@@ -181,6 +207,7 @@ def test_batched_adjoint_equals_plain_and_oracle(B, orc):
     ref_sum = np.zeros_like(alm_h)
     for i, (L, M, x) in enumerate(DETS):
         a_t = truncate_sky(alm_h, LSKY, L)
+        B.set_tile(B.TC_OP_ADJ, walk_R(8, x))
         ga, gb = B.totalconv_adj_x(L, M, x, dev(a_t), dets[i]["blm"], dets[i]["Cbar"])
         assert torch.equal(gb.cpu(), res[0][1][i]), f"detector {i}: beam gradient batched != plain"
         sky_sum += pad_sky(ga.cpu().numpy(), L, LSKY)
@@ -234,6 +261,7 @@ def test_batched16_full_size_sampled(B, orc, t):
 
 def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
     plan = B.Plan(B.TC_OP_FWD, dets, w.lmax, alm)
+    R_plan = plan.tile
     plan.execute()
     torch.cuda.synchronize()
     plan.close()
@@ -250,6 +278,7 @@ def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
         idx = torch.from_numpy(((mb + M) * (L + 1) + ms).astype(np.int64)).to("cuda")
         got = det["C"].reshape(-1, x.size).index_select(0, idx).cpu()
         a_t = truncate_sky(alm_h, w.lmax, L)
+        B.set_tile(B.TC_OP_FWD, walk_R(R_plan, x))
         plain = B.totalconv_fwd_x(L, M, x, dev(a_t), det["blm"])
         same = torch.equal(plain.reshape(-1, x.size).index_select(0, idx).cpu(), got)
         del plain
@@ -278,6 +307,7 @@ def test_plan_follows_beams_changed_between_executions(B, first):
              "C": torch.empty((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda")}
             for b in order[0]]
     plan = B.Plan(B.TC_OP_FWD, dets, L, alm)
+    B.set_tile(B.TC_OP_FWD, walk_R(plan.tile, x))   # the plain calls at the plan's walk tile
     try:
         for beams in order:
             for d, b in zip(dets, beams):
@@ -290,4 +320,5 @@ def test_plan_follows_beams_changed_between_executions(B, first):
                 assert torch.equal(plain, d["C"]), "plan result differs from the plain call"
     finally:
         plan.close()
+        B.set_tile_ex(B.TC_OP_FWD, 0, 0, 0)
     say(f"plan made on {first} beams follows in-place beam changes")
