@@ -1283,20 +1283,26 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
 
     // ---- capture the graph on a private stream (the caller's stream may be the legacy one).  The
     // launches of the different R run side by side: the costliest on the capture stream, each other
-    // on a stream of its own forked from it and joined back before the epilogues.
-    const int nside = launches.empty() ? 0 : (int)launches.size() - 1;
+    // on a stream of its own forked from it and joined back before the epilogues.  The adjoint's
+    // epilogues (each too small to fill the device) run side by side the same way: the summed sky
+    // gradient on the capture stream, the beam gradients spread over the side streams.
+    int nbeam = 0;
+    for (int i = 0; i < ndet; ++i) nbeam += (op == TC_OP_ADJ && dets[i].blm_bar) ? 1 : 0;
+    const int nside = std::max(launches.empty() ? 0 : (int)launches.size() - 1, std::min(nbeam, 8));
     std::vector<hipStream_t> side(nside, nullptr);
     std::vector<hipEvent_t> joins(nside, nullptr);
-    hipEvent_t fork = nullptr;
+    hipEvent_t fork = nullptr, fork2 = nullptr;
     hipStream_t cs = nullptr;
     auto release_capture = [&] {
         for (hipStream_t q : side) if (q) (void)hipStreamDestroy(q);
         for (hipEvent_t e : joins) if (e) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
+        if (fork2) (void)hipEventDestroy(fork2);
         if (cs) (void)hipStreamDestroy(cs);
     };
     rc = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (!rc) rc = (int)hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (!rc) rc = (int)hipEventCreateWithFlags(&fork2, hipEventDisableTiming);
     for (int k = 0; k < nside && !rc; ++k) {
         rc = (int)hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
         if (!rc) rc = (int)hipEventCreateWithFlags(&joins[k], hipEventDisableTiming);
@@ -1308,7 +1314,8 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     for (int i = 0; i < ndet && !rc && op == TC_OP_FWD; ++i)   // beam row signs, on every execution
         rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, reinterpret_cast<int*>(dm + sym_off[i]),
                                       cs);
-    if (!rc && nside > 0) rc = (int)hipEventRecord(fork, cs);
+    const int nfork = (int)launches.size() - 1;
+    if (!rc && nfork > 0) rc = (int)hipEventRecord(fork, cs);
     for (size_t k = 0; k < launches.size() && !rc; ++k) {
         hipStream_t q = k == 0 ? cs : side[k - 1];
         if (k > 0) rc = (int)hipStreamWaitEvent(q, fork, 0);
@@ -1321,13 +1328,20 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
                                       l.n, l.tile, q);
         if (!rc && k > 0) rc = (int)hipEventRecord(joins[k - 1], q);
     }
-    for (int k = 0; k < nside && !rc; ++k) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
+    for (int k = 0; k < nfork && !rc; ++k) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
     if (!rc && op == TC_OP_ADJ) {
-        if (alm_bar)
+        const int nb = std::min(nbeam, nside);   // side streams the beam epilogues take
+        if (nb > 0) rc = (int)hipEventRecord(fork2, cs);
+        for (int k = 0; k < nb && !rc; ++k) rc = (int)hipStreamWaitEvent(side[k], fork2, 0);
+        for (int i = 0, b = 0; i < ndet && !rc; ++i)
+            if (dets[i].blm_bar) rc = tc::launch_adj_beam(ea[i], nb > 0 ? side[b++ % nb] : cs);
+        if (!rc && alm_bar)
             rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
                                           cs);
-        for (int i = 0; i < ndet && !rc; ++i)
-            if (dets[i].blm_bar) rc = tc::launch_adj_beam(ea[i], cs);
+        for (int k = 0; k < nb && !rc; ++k) {
+            rc = (int)hipEventRecord(joins[k], side[k]);
+            if (!rc) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
+        }
     }
     hipGraph_t g = nullptr;
     const int rc_end = (int)hipStreamEndCapture(cs, &g);
