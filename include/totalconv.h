@@ -272,12 +272,16 @@ int totalconv_adj_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, i
  *                evaluated on that grid requires)
  *   cube         out: [nring][nalpha][ngamma] doubles, 16-byte aligned
  *   workspace    at least totalconv_datacube_workspace_bytes(...) bytes: the
- *                phase and twiddle tables and the alpha sums of one ring chunk
- *                (at most 2 GiB; rings are processed in chunks)
+ *                phase and twiddle tables and the alpha sums of two ring chunks
+ *                (rings are processed in chunks of about 768 MB of alpha sums, the
+ *                sums over mb of one chunk formed while the FFTs of the chunk
+ *                before run on a second stream of the library)
  * TC_EUNSUPPORTED if the device allows less LDS per workgroup than the FFT of
  * length ngamma needs (8.5 * ngamma + 16 bytes).
+ * totalconv_datacube_ring_chunk returns the rings per chunk (0 for bad sizes).
  */
 size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int nalpha, int ngamma);
+int totalconv_datacube_ring_chunk(int lmax, int mbmax, int nring, int nalpha, int ngamma);
 int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma,
                        double* cube, void* workspace, size_t ws_bytes, void* stream);
 
@@ -286,7 +290,7 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
  * knob of this implementation).  Each lane walks R chains; a workgroup covers
  * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8}),
  * TC_OP_FWD_POL (R in {2, 4}), TC_OP_WIGNER (R in {1, 4}) or TC_OP_MATRIX (R in
- * {1, 2}); for TC_OP_CUBE, R > 0 caps the rings the data cube processes per chunk
+ * {1, 2}); for TC_OP_CUBE, R > 0 sets the rings the data cube processes per chunk
  * (and so its workspace).  R = 0 restores the built-in choice.  Affects
  * the workspace sizes reported afterwards.  Returns TC_EINVAL for other values.
  * Not synchronised: set it from the thread that issues the calls.
@@ -360,8 +364,8 @@ int tc_plan_destroy(void* plan);
  * from then on every wigner_d_rings / totalconv_fwd / totalconv_adj /
  * totalconv_fwd_pol call records one pair (under op TC_OP_WIGNER, TC_OP_FWD,
  * TC_OP_ADJ, TC_OP_FWD_POL) on its own stream, directly before and after its
- * recursion kernel; totalconv_datacube records one TC_OP_CUBE pair around the
- * two kernels of each ring chunk, wigner_d_matrix one TC_OP_MATRIX pair (for the adjoint: without the two short epilogue kernels
+ * recursion kernel; totalconv_datacube records one TC_OP_CUBE pair around all
+ * of its kernels (both streams), wigner_d_matrix one TC_OP_MATRIX pair (for the adjoint: without the two short epilogue kernels
  * that finish the gradients; totalconv_adj_pol records one TC_OP_ADJ pair per
  * cotangent), reusing the pairs cyclically.  n = 0 releases the events and
  * stops the recording.  Calls must then run on streams of that device.

@@ -96,6 +96,8 @@ def lib():
             L.wigner_d_matrix_workspace_bytes.argtypes = [I, I]
             L.totalconv_datacube_workspace_bytes.restype = S
             L.totalconv_datacube_workspace_bytes.argtypes = [I, I, I, I, I]
+            L.totalconv_datacube_ring_chunk.restype = I
+            L.totalconv_datacube_ring_chunk.argtypes = [I, I, I, I, I]
             L.totalconv_datacube.restype = I
             L.totalconv_datacube.argtypes = [I, I, I, P, I, I, P, P, S, P]
             L.tc_timing_enable.restype = I
@@ -436,6 +438,11 @@ def totalconv_datacube(lmax: int, mbmax: int, C, nalpha: int, ngamma: int, out=N
                                   ws.numel(), stream)
     _check("totalconv_datacube", rc)
     return out
+
+
+def datacube_ring_chunk(lmax: int, mbmax: int, nring: int, nalpha: int, ngamma: int) -> int:
+    """Rings the data cube processes per chunk (0 for sizes it refuses)."""
+    return int(lib().totalconv_datacube_ring_chunk(lmax, mbmax, nring, nalpha, ngamma))
 
 
 def set_tile(op: int, R: int):

@@ -7,7 +7,8 @@
 // taken from C_{-mb,-msky} = conj(C_{mb,msky}) (real sky and beam, Sec. 4.2.3), so
 // that c is real.
 //
-// Two passes, both bound by HBM bandwidth:
+// Two passes, both bound by HBM bandwidth (the host runs them over ring chunks, the alpha pass of
+// one chunk beside the gamma pass of the chunk before):
 //  1. k_cube_alpha: P[j][a][k] = sum_mb E[mb][a] C[mb][k][j] for k = msky >= 0 -- the
 //     short sum over mb, done directly with the host's phase table E (read into scalar
 //     registers, four phases per load), and the
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(256) k_cube_gamma(const CubeArgs c)
 
 }  // namespace
 
-int launch_cube(const CubeArgs& c, void* stream)
+int launch_cube_alpha(const CubeArgs& c, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     dim3 g1((c.nring_chunk + CA_T - 1) / CA_T, (c.lmax + 1 + CA_T - 1) / CA_T);
@@ -358,8 +359,12 @@ int launch_cube(const CubeArgs& c, void* stream)
         hipLaunchKernelGGL(k_cube_alpha<16>, g1, dim3(256), 0, s, c, C, E, P);
     else
         hipLaunchKernelGGL(k_cube_alpha<32>, g1, dim3(256), 0, s, c, C, E, P);
-    int rc = (int)hipGetLastError();
-    if (rc) return rc;
+    return (int)hipGetLastError();
+}
+
+int launch_cube_gamma(const CubeArgs& c, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
     const int H = c.ngamma / 2;
     const size_t sh2 = sizeof(double2) * ((size_t)H + (H >> 4) + 1);
     if (H <= 4096)

@@ -550,11 +550,16 @@ MatrixLayout make_matrix_layout(int l, int nring)
 
 // ---------------------------------------------------------------- data cube
 
-constexpr size_t kCubeChunkBytes = (size_t)1 << 31;   // alpha sums held per ring chunk
+// Alpha sums held per ring chunk.  Two chunks are in flight: the alpha pass of one chunk runs
+// beside the FFTs of the chunk before.  (Chunks small enough for both to stay in the 256 MB
+// last-level cache, 64 rings at lmax 4096, lose more to the ramp of each launch than the cache
+// saves; from about 256 rings on the time no longer depends on the size.)
+constexpr size_t kCubeChunkBytes = (size_t)768 << 20;
 
 struct CubeLayout {
     size_t phase = 0, tw = 0, P = 0, total = 0;
-    int chunk = 0;
+    size_t P_bytes = 0;   // one of the two P buffers
+    int chunk = 0;        // rings per chunk
 };
 
 int g_cube_chunk = 0;   // rings per chunk of the data cube (tc_set_tile); 0 = built-in
@@ -563,14 +568,33 @@ CubeLayout make_cube_layout(int lmax, int mbmax, int nring, int nalpha, int ngam
 {
     CubeLayout C;
     const size_t per_ring = (size_t)16 * (size_t)nalpha * (size_t)(lmax + 1);
-    C.chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nring, kCubeChunkBytes / per_ring));
-    if (g_cube_chunk > 0) C.chunk = std::min(C.chunk, g_cube_chunk);
+    size_t chunk = std::max<size_t>(1, kCubeChunkBytes / per_ring);
+    if (chunk >= 16) chunk = chunk / 16 * 16;   // whole 16-ring tiles of the alpha pass
+    if (g_cube_chunk > 0) chunk = (size_t)g_cube_chunk;
+    C.chunk = (int)std::min<size_t>((size_t)nring, chunk);
     size_t off = 0;
     C.phase = off; off = align_up(off + (size_t)16 * ((nalpha + 3) / 4 * 4) * (2 * mbmax + 1));
     C.tw = off;    off = align_up(off + (size_t)16 * ngamma);
-    C.P = off;     off = align_up(off + per_ring * (size_t)C.chunk);
+    C.P_bytes = align_up(per_ring * (size_t)C.chunk);
+    C.P = off;     off += 2 * C.P_bytes;
     C.total = off;
     return C;
+}
+
+// The second stream of the data cube on device dev (created on first use, default priority,
+// kept until the process ends); hipError_t value.
+int cube_side_stream(int dev, hipStream_t* s)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    if (dev < 0 || dev >= 64) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) {
+        const int rc = (int)hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (rc) return rc;
+    }
+    *s = streams[dev];
+    return 0;
 }
 
 int check_cube(int lmax, int mbmax, int nring, int nalpha, int ngamma)
@@ -649,6 +673,14 @@ size_t totalconv_datacube_workspace_bytes(int lmax, int mbmax, int nring, int na
     return rc ? 0 : make_cube_layout(lmax, mbmax, nring, nalpha, ngamma).total;
 }
 
+int totalconv_datacube_ring_chunk(int lmax, int mbmax, int nring, int nalpha, int ngamma)
+{
+    const std::string saved = g_error;
+    const int rc = check_cube(lmax, mbmax, nring, nalpha, ngamma);
+    g_error = saved;
+    return rc ? 0 : make_cube_layout(lmax, mbmax, nring, nalpha, ngamma).chunk;
+}
+
 int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalpha, int ngamma, double* cube,
                        void* workspace, size_t ws_bytes, void* stream)
 {
@@ -696,17 +728,42 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
     c.C = C;
     c.phase = reinterpret_cast<const double*>(static_cast<char*>(workspace) + CL.phase);
     c.tw = reinterpret_cast<const double*>(static_cast<char*>(workspace) + CL.tw);
-    c.P = reinterpret_cast<double*>(static_cast<char*>(workspace) + CL.P);
     c.cube = cube;
-    for (int r0 = 0; r0 < nring; r0 += CL.chunk) {
-        c.ring0 = r0;
-        c.nring_chunk = std::min(CL.chunk, nring - r0);
-        if ((long long)c.nring_chunk * nalpha > 0x7fffffffLL)
-            return fail(TC_EUNSUPPORTED, "data cube: too many rows in one launch");
-        rc = timed_launch(TC_OP_CUBE, stream, [&] { return tc::launch_cube(c, stream); });
-        if (rc) return hip_fail(rc, "totalconv_datacube launch");
-    }
-    return TC_OK;
+    if ((long long)CL.chunk * nalpha > 0x7fffffffLL) return fail(TC_EUNSUPPORTED, "data cube: too many rows in one launch");
+    // Chunk k: the alpha pass on `stream` into P buffer k mod 2, then the gamma pass on the
+    // library's second stream of this device; the alpha pass of chunk k + 2 waits for the gamma
+    // pass of chunk k (same buffer), the call's end waits for every gamma pass.
+    hipStream_t A = static_cast<hipStream_t>(stream), G = nullptr;
+    if ((rc = cube_side_stream(dev, &G))) return hip_fail(rc, "data cube: second stream");
+    hipEvent_t ev[5] = {};   // start, alpha done (x2), gamma done (x2)
+    for (hipEvent_t& e : ev)
+        if (!rc) rc = (int)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    auto release = [&] {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);   // released once their work completes
+    };
+    if (rc) { release(); return hip_fail(rc, "data cube: events"); }
+    const int nchunk = (nring + CL.chunk - 1) / CL.chunk;
+    rc = timed_launch(TC_OP_CUBE, stream, [&] {
+        int r = (int)hipEventRecord(ev[0], A);
+        if (!r) r = (int)hipStreamWaitEvent(G, ev[0], 0);
+        for (int k = 0; k < nchunk && !r; ++k) {
+            const int b = k & 1;
+            c.ring0 = k * CL.chunk;
+            c.nring_chunk = std::min(CL.chunk, nring - c.ring0);
+            c.P = reinterpret_cast<double*>(static_cast<char*>(workspace) + CL.P + (size_t)b * CL.P_bytes);
+            if (k >= 2) r = (int)hipStreamWaitEvent(A, ev[3 + b], 0);
+            if (!r) r = tc::launch_cube_alpha(c, A);
+            if (!r) r = (int)hipEventRecord(ev[1 + b], A);
+            if (!r) r = (int)hipStreamWaitEvent(G, ev[1 + b], 0);
+            if (!r) r = tc::launch_cube_gamma(c, G);
+            if (!r) r = (int)hipEventRecord(ev[3 + b], G);
+        }
+        for (int b = 0; b < std::min(nchunk, 2) && !r; ++b) r = (int)hipStreamWaitEvent(A, ev[3 + b], 0);
+        return r;
+    });
+    release();
+    return rc ? hip_fail(rc, "totalconv_datacube launch") : TC_OK;
 }
 
 }  // extern "C"

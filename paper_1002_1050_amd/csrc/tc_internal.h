@@ -106,12 +106,13 @@ struct CubeArgs {
     const double* C;       // [2M+1][L+1][nring] complex (totalconv_fwd output)
     const double* phase;   // [2M+1][nalpha rounded up to 4] complex, e^{-2 pi i mb a / nalpha} (pad: 0)
     const double* tw;      // [ngamma] complex, e^{-2 pi i m / ngamma}
-    double* P;             // [nring_chunk][nalpha][L+1] complex, alpha sums
+    double* P;             // [nring_chunk][nalpha][L+1] complex, alpha sums of the chunk
     double* cube;          // [nring][nalpha][ngamma] real
 };
 
 // Data-cube launchers (tc_cube.hip).
-int launch_cube(const CubeArgs& c, void* stream);
+int launch_cube_alpha(const CubeArgs& c, void* stream);   // P of the chunk from C
+int launch_cube_gamma(const CubeArgs& c, void* stream);   // the chunk's cube rows from P
 int cube_set_lds_limits();
 
 // Kernel launchers (tc_kernels.hip).  Return a hipError_t value (0 on success).

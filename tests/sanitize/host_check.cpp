@@ -13,7 +13,8 @@ namespace tc {
 // Launchers are never reached without a device; each returns hipErrorInvalidDeviceFunction.
 constexpr int kNoKernel = 98;
 int launch_matrix(const MatrixArgs&, int, void*) { return kNoKernel; }
-int launch_cube(const CubeArgs&, void*) { return kNoKernel; }
+int launch_cube_alpha(const CubeArgs&, void*) { return kNoKernel; }
+int launch_cube_gamma(const CubeArgs&, void*) { return kNoKernel; }
 int cube_set_lds_limits() { return kNoKernel; }
 int launch_wigner(const WignerArgs&, Tile, void*) { return kNoKernel; }
 int launch_fwd(const FwdArgs&, Tile, void*) { return kNoKernel; }

@@ -99,20 +99,26 @@ def test_cube_rejects_bad_grids(B):
 
 
 def test_cube_ring_chunks_give_the_same_cube(B):
-    """Rings processed in chunks (here 3 at a time, 6 chunks) give the unchunked cube bit for bit."""
+    """Rings processed in chunks (here 3 at a time, 6 chunks through the two alpha-sum buffers,
+    the FFTs of each chunk on the library's second stream) give the one-chunk cube bit for bit,
+    call after call (one timing record per call)."""
     L, M, n, Na, Ng = 20, 3, 17, 7, 64
     C = torch.from_numpy(random_C(L, M, n, 77)).cuda()
+    assert B.datacube_ring_chunk(L, M, n, Na, Ng) == n            # one chunk by default
     whole = B.totalconv_datacube(L, M, C, Na, Ng).clone()
     B.set_tile(B.TC_OP_CUBE, 3)
     try:
+        assert B.datacube_ring_chunk(L, M, n, Na, Ng) == 3
         B.timing_enable(16)
-        chunked = B.totalconv_datacube(L, M, C, Na, Ng)
-        torch.cuda.synchronize()
-        assert len(B.timing_read(B.TC_OP_CUBE, 16)) == 6
+        for _ in range(3):
+            out = torch.full((n, Na, Ng), float("nan"), dtype=torch.float64, device="cuda")
+            chunked = B.totalconv_datacube(L, M, C, Na, Ng, out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(whole, chunked)
+        assert len(B.timing_read(B.TC_OP_CUBE, 16)) == 3
     finally:
         B.timing_enable(0)
         B.set_tile(B.TC_OP_CUBE, 0)
-    assert torch.equal(whole, chunked)
 
 
 def test_cube_full_size_from_the_forward_sampled(B, orc):
@@ -125,13 +131,11 @@ def test_cube_full_size_from_the_forward_sampled(B, orc):
     Na, Ng = 2 * M + 1, 2 * L
     C = B.totalconv_fwd_x(L, M, x, torch.from_numpy(w.alm()).cuda(), torch.from_numpy(w.blm()).cuda())
     say(f"datacube full size L={L} M={M} nring={x.size} nalpha={Na} ngamma={Ng}")
-    B.timing_enable(64)
     cube = B.totalconv_datacube(L, M, C, Na, Ng)
     torch.cuda.synchronize()
-    nchunk = len(B.timing_read(B.TC_OP_CUBE, 64))
-    B.timing_enable(0)
-    chunk = (1 << 31) // (16 * Na * (L + 1))      # rings per chunk: alpha sums of a chunk within 2 GiB
-    assert nchunk == -(-x.size // chunk)
+    chunk = B.datacube_ring_chunk(L, M, x.size, Na, Ng)
+    assert 16 <= chunk < x.size
+    nchunk = -(-x.size // chunk)
     rings = np.unique(np.clip(np.array([0, chunk - 1, chunk, 3 * chunk + 5, x.size // 2, x.size - 1]), 0, x.size - 1))
     say(f"  {nchunk} ring chunks; sampled rings {rings.tolist()}")
     sel = torch.from_numpy(rings).cuda()
