@@ -290,7 +290,8 @@ int totalconv_datacube(int lmax, int mbmax, int nring, const double* C, int nalp
  * knob of this implementation).  Each lane walks R chains; a workgroup covers
  * 256*R ring slots of one column.  op = TC_OP_FWD or TC_OP_ADJ (R in {2, 4, 8}),
  * TC_OP_FWD_POL (R in {2, 4}), TC_OP_WIGNER (R in {1, 4}) or TC_OP_MATRIX (R in
- * {1, 2}); for TC_OP_CUBE, R > 0 sets the rings the data cube processes per chunk
+ * {1, 2}: one-wave workgroups with R rows per lane in place of the built-in two-wave
+ * workgroups with one row per lane); for TC_OP_CUBE, R > 0 sets the rings the data cube processes per chunk
  * (and so its workspace).  R = 0 restores the built-in choice.  Affects
  * the workspace sizes reported afterwards.  Returns TC_EINVAL for other values.
  * Not synchronised: set it from the thread that issues the calls.

@@ -634,8 +634,9 @@ int wigner_d_matrix_x(int l, int nring, const double* cosbeta, double* d, void* 
     if (!workspace) return fail(TC_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
         return fail(TC_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-    const int R = g_matrix_R > 0 ? g_matrix_R : 1;
-    const int ntile = (l + 1 + 64 * R - 1) / (64 * R);   // one-wave workgroups of R rows per lane
+    const int R = g_matrix_R;   // 0: the built-in variant
+    const int rows = tc::matrix_rows_per_group(R);
+    const int ntile = (l + 1 + rows - 1) / rows;
     if ((long long)ntile * 2 * nring > 0x7fffffffLL)
         return fail(TC_EUNSUPPORTED, "launch of %lld workgroups exceeds the grid limit", (long long)ntile * 2 * nring);
     std::vector<char> img(M.total, 0);

@@ -97,7 +97,8 @@ struct MatrixArgs {
     double* d;             // [nring][2l+1][2l+1], d[j][m+l][m'+l]
 };
 
-int launch_matrix(const MatrixArgs& a, int R, void* stream);
+int launch_matrix(const MatrixArgs& a, int variant, void* stream);
+int matrix_rows_per_group(int variant);   // rows m one workgroup walks (0: no such variant)
 
 // Data cube (eq. conviqt) of rings [ring0, ring0 + nring_chunk).
 struct CubeArgs {

@@ -101,10 +101,19 @@ __device__ __forceinline__ unsigned image_off(int side, int k, int l, int W, int
     return (unsigned)((row + l) * W + (col + l));
 }
 
+// Sync of the held values before and after a flush: within the wave for one-wave workgroups,
+// a workgroup barrier otherwise.
+template <int NT>
+__device__ __forceinline__ void held_sync()
+{
+    if constexpr (NT == 64) wave_lds_fence();
+    else __syncthreads();
+}
+
 template <int R, int NT, int TB, int FL>
 __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
 {
-    static_assert(NT == 64, "one wave per workgroup");
+    static_assert(NT % 64 == 0, "whole waves");
     static_assert(TB % FL == 0 && FL % MS_TS == 0 && (NT % FL == 0 || FL % NT == 0), "flush period");
     constexpr int LPR = FL < NT ? FL : NT;    // lanes per row segment in a flush
     constexpr int RPS = NT / LPR;             // rows per flush store
@@ -158,6 +167,13 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
 
     // step s: from m' = l - s to m' - 1; steps needed: l - m_lo
     const int nsteps = l - m_lo;
+    // Steps s <= full have m' = l - s >= every row of the workgroup; a group of MS_TS steps all
+    // within them (and all followed by a step of the walk) takes the fast path below: no
+    // per-step checks, the coefficients of the group read together, the two images along m'
+    // through pointers moved by one output row per step (inc1 = +-W elements).
+    const int m_hi = min(l, m_base + NT * R - 1);
+    const int fast_last = pole ? -1 : min(nsteps - 1, l - m_hi);
+    const long long inc1 = side ? (long long)W : -(long long)W;
     for (int t = tid; t < TB; t += NT) {
         const int mp = l - t;
         double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -192,6 +208,39 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
                 }
                 scaled = wave_any_m(any);
             }
+            const int sg = s0 + t0;
+            if (sg + MS_TS - 1 <= fast_last) {
+                double4 kk[MS_TS];
+#pragma unroll
+                for (int t = 0; t < MS_TS; ++t) kk[t] = cf[buf][t0 + t];
+                double* p1[R];
+                double* p3[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int m = mrow[r] < 0 ? side : mrow[r];   // lanes without a row store nothing
+                    p1[r] = out + image_off(side, 1, l, W, m, l - sg);
+                    p3[r] = out + image_off(side, 3, l, W, m, l - sg);
+                }
+#pragma unroll
+                for (int t = 0; t < MS_TS; ++t) {
+                    const int h = (t0 + t) % FL;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double v = E[r] == 0 ? d[r] : ldexp(d[r], E[r]);
+                        const double u = rs[r] * v;
+                        held[r][h][tid] = u;
+                        if (mrow[r] >= 0) {
+                            p1[r][t * inc1] = s_r[r] * u;
+                            p3[r][-t * inc1] = u;
+                        }
+                        s_r[r] = -s_r[r];
+                        const double w = fma(xm[r], kk[t].x, kk[t].y);
+                        const double dn = fma(-kk[t].z, dp[r], w * d[r]);
+                        dp[r] = d[r];
+                        d[r] = dn;
+                    }
+                }
+            } else {
 #pragma unroll
             for (int t = 0; t < MS_TS; ++t) {
                 const int s = s0 + t0 + t;
@@ -223,13 +272,41 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
                     }
                 }
             }
+            }
             // images 0 and 2 of the held steps, after every FL steps and after the last:
             // FL lanes per row, NT / FL rows per store
             const int done = s0 + t0 + MS_TS;
             if ((t0 + MS_TS) % FL == 0 || done > nsteps) {
                 const int sb = s0 + ((t0 + MS_TS - 1) / FL) * FL;
                 const int n = min(FL, nsteps + 1 - sb);
-                wave_lds_fence();
+                held_sync<NT>();
+                if (n == FL && sb + FL - 1 <= fast_last) {
+                    // every held step has m' >= every row: per lane one m' (tq), rows q stepped by RPS,
+                    // image 0 one output row further per RPS rows, image 2 one row back
+                    const int q0 = tid / LPR;
+                    const long long rstep = (long long)RPS * W;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+#pragma unroll
+                        for (int c = 0; c < FL; c += LPR) {
+                            const int tq = c + tid % LPR;
+                            const int mpf = l - (sb + tq);
+                            const int m0 = m_base + r * NT + q0;
+                            double* p0 = out + image_off(side, 0, l, W, m0, mpf);
+                            double* p2 = out + image_off(side, 2, l, W, m0, mpf);
+                            bool odd = ((m0 - mpf) & 1) != 0;
+                            for (int q = q0, k = 0; q < NT; q += RPS, ++k) {
+                                const int m = m0 + (q - q0);
+                                const double u = held[r][tq][q];
+                                if (m >= side && m <= l) {
+                                    p0[k * rstep] = u;
+                                    p2[-k * rstep] = odd ? -u : u;
+                                }
+                                odd = (RPS & 1) ? !odd : odd;
+                            }
+                        }
+                    }
+                } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     for (int q = tid / LPR; q < NT; q += RPS) {
@@ -246,7 +323,8 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
                         }
                     }
                 }
-                wave_lds_fence();
+                }
+                held_sync<NT>();
             }
         }
         if (s0 + TB <= nsteps) {
@@ -267,18 +345,32 @@ __global__ void __launch_bounds__(NT) k_wigner_row(const MatrixArgs a)
 
 }  // namespace
 
-// One-wave workgroups: a row walk is long and sequential, so many small workgroups
-// keep more of them in flight.
-int launch_matrix(const MatrixArgs& a, int R, void* stream)
+// Built variants (id: R rows per lane, NT lanes, TB-step coefficient blocks, FL-step flushes).
+// Id 0, the built-in: two-wave workgroups of 128 rows flushing every 128 steps, so that both
+// image streams leave in 1 KB row segments (scattered 512-byte segments reach about two thirds
+// of the write bandwidth of 1 KB ones on MI355X); the LDS of the flush buffer (133 KB) allows
+// one workgroup per CU.  Ids 1 and 2: one-wave workgroups, 512-byte segments, R = 1 or 2.
+#define TC_MATRIX_VARIANTS(X) X(0, 1, 128, 128, 128) X(1, 1, 64, 64, 64) X(2, 2, 64, 64, 64)
+
+int matrix_rows_per_group(int v)
+{
+#define X(id, r, nt, tb, fl) if (v == id) return r * nt;
+    TC_MATRIX_VARIANTS(X)
+#undef X
+    return 0;
+}
+
+int launch_matrix(const MatrixArgs& a, int v, void* stream)
 {
     const int blocks = a.ntile * 2 * a.nring;
-    if (R == 1)
-        hipLaunchKernelGGL((k_wigner_row<1, 64, MS_TB, MS_FL>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
-    else if (R == 2)
-        hipLaunchKernelGGL((k_wigner_row<2, 64, MS_TB, MS_FL>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, a);
-    else
-        return (int)hipErrorInvalidValue;
-    return (int)hipGetLastError();
+#define X(id, r, nt, tb, fl)                                                                                     \
+    if (v == id) {                                                                                               \
+        hipLaunchKernelGGL((k_wigner_row<r, nt, tb, fl>), dim3(blocks), dim3(nt), 0, (hipStream_t)stream, a);   \
+        return (int)hipGetLastError();                                                                           \
+    }
+    TC_MATRIX_VARIANTS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 }  // namespace tc

@@ -73,14 +73,18 @@ def test_matrix_large_l_sampled_and_orthogonal(B, orc, l, gate):
 
 
 def test_matrix_tiles_agree(B):
+    """The built-in two-wave workgroups (128-step flushes, a partial last row tile at l 1500) and
+    the one-wave R 1 and R 2 builds write the same matrix bit for bit, poles included."""
     l = 1500
-    x = RINGS[2:7]
+    x = np.concatenate([RINGS[2:7], [1.0, -1.0]])
+    B.set_tile(B.TC_OP_MATRIX, 0)
+    c = B.wigner_d_matrix_x(l, x)
     B.set_tile(B.TC_OP_MATRIX, 1)
     a = B.wigner_d_matrix_x(l, x)
     B.set_tile(B.TC_OP_MATRIX, 2)
     b = B.wigner_d_matrix_x(l, x)
     B.set_tile(B.TC_OP_MATRIX, 0)
-    assert torch.equal(a, b)
+    assert torch.equal(a, b) and torch.equal(a, c)
 
 
 def test_matrix_benchmark_launch_sampled(B, orc):
