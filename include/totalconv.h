@@ -314,10 +314,15 @@ int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR);
 
 /*
  * Batched plan: many detectors -- each with its own beam, mbmax, lmax and ring
- * set -- convolved with one shared sky in a single persistent launch that takes
- * (detector, column, ring tile) items from a queue ordered longest first, all
- * captured in one HIP graph (the batching is not in the paper; every item
- * computes the same sum as totalconv_fwd / totalconv_adj).
+ * set -- convolved with one shared sky, all captured in one HIP graph (the
+ * batching is not in the paper).  Detectors with the same lmax and the same ring
+ * cosines share walks of the recursion in the forward (up to four per walk, the
+ * largest mbmax first; one even / odd walk feeds every member's output, as the
+ * polarised pairs of Sec. 4.1's footnote share theirs); one workgroup per work
+ * item (walk or detector, column, ring tile), the items longest first; one launch
+ * per chains-per-lane R, the launches of different R on parallel graph branches.
+ * Every output equals what totalconv_fwd / totalconv_adj computes for that
+ * detector at the R the plan walks it with, bit for bit.
  */
 typedef struct tc_detector {
     int lmax;                /* 0 <= mbmax <= lmax <= lmax_sky                     */
@@ -341,10 +346,9 @@ typedef struct tc_detector {
  * released by tc_plan_destroy).  Creation is synchronous on `stream`.  The
  * pointed-to data may change between executions: each execution reads the
  * beams, sky and cotangents afresh (including, for the forward, which beam rows
- * are equal up to a sign, as totalconv_fwd does).  A forward plan also reads the
- * beams once at creation: if every row pair b_{l,-mb} = +-b_{l,mb} then, the
- * queue kernel is built for four waves per SIMD instead of three (a speed
- * choice only; results do not depend on it).
+ * are equal up to a sign, as totalconv_fwd does).  A detector is walked with the
+ * largest R not above the plan's (tc_plan_tile) whose 256 R ring slots its rings
+ * still fill more than half of (R halved while 128 R >= its slots).
  */
 int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int lmax_sky,
                    const double* alm, double* alm_bar, void* stream);
@@ -352,7 +356,7 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
 /* Enqueue the plan's graph on `stream` (asynchronous). */
 int tc_plan_execute(void* plan, void* stream);
 
-/* Device bytes the plan owns, and the R of its persistent kernel. */
+/* Device bytes the plan owns, and its largest R (the R of op's current tile). */
 size_t tc_plan_device_bytes(void* plan);
 int tc_plan_tile(void* plan);
 

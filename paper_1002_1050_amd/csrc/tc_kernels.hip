@@ -53,7 +53,7 @@ static_assert(RS_STEPS % TS == 0 && GROWTH_BITS_PER_STEP * RS_STEPS < 1023 && SK
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-// Loads and stores through a pointer taken from a struct in memory (the persistent
+// Loads and stores through a pointer taken from a struct in memory (the batched
 // kernels read their arguments from a device array) are marked as global memory, so that
 // they compile to global rather than flat instructions, with a scalar base where the
 // address is uniform.
