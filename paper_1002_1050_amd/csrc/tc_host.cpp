@@ -506,8 +506,10 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
     a.ring = ring_ptrs(workspace, L, nring);
     a.slots = reinterpret_cast<const int*>(static_cast<char*>(workspace) + L.slots);
     a.col = col_ptrs(workspace, L);
-    a.U = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
-    a.V = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
+    a.npair = 1;
+    a.pmbmax[0] = mbmax;
+    a.U[0] = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.U);
+    a.V[0] = reinterpret_cast<double*>(static_cast<char*>(workspace) + L.V);
     a.P = L.P;
     for (int k = 0; k < ncot; ++k) {
         const int p0 = sum ? 0 : k, p1 = sum ? npair : k + 1;   // pairs served by cotangent k
@@ -515,14 +517,14 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
         for (int p = p0; p < p1; ++p)
             need |= (alm_bar && alm_bar[p]) || (blm_bar && blm_bar[p]);
         if (!need) continue;
-        a.Cbar = Cbar[k];
+        a.Cbar[0] = Cbar[k];
         // one workgroup per column walks its ring tiles in order: tile 0 writes U and V, later tiles add
         rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
         if (rc) return hip_fail(rc, "totalconv_adj launch");
         for (int p = p0; p < p1; ++p) {
             tc::EpiArgs e{};
             e.lmax = lmax; e.mbmax = mbmax; e.P = L.P; e.sky_lmax = lmax;
-            e.U = a.U; e.V = a.V; e.alm = alm[p]; e.blm = blm[p];
+            e.U = a.U[0]; e.V = a.V[0]; e.alm = alm[p]; e.blm = blm[p];
             e.alm_bar = alm_bar ? alm_bar[p] : nullptr;
             e.blm_bar = blm_bar ? blm_bar[p] : nullptr;
             if ((rc = tc::launch_adj_epilogue(e, stream))) return hip_fail(rc, "totalconv_adj epilogue launch");
@@ -1147,8 +1149,8 @@ struct Walk {
 
 // Walks of a plan: detectors with the same lmax and the same ring cosines (bit for bit) form
 // one class, whose walks take the class's R; each class, ordered by mbmax (largest first, then
-// by index), is cut into walks of as many detectors as a forward walk at that R serves (one for
-// the adjoint).  Walks come in the order of their first detector.
+// by index), is cut into walks of as many detectors as a walk at that tile serves.  Walks come
+// in the order of their first detector.
 std::vector<Walk> group_detectors(int op, int ndet, const tc_detector* dets,
                                   const std::vector<std::vector<double>>& xr, const tc::Tile& t)
 {
@@ -1170,7 +1172,7 @@ std::vector<Walk> group_detectors(int op, int ndet, const tc_detector* dets,
         std::stable_sort(c.begin(), c.end(), [&](int a, int b) { return dets[a].mbmax > dets[b].mbmax; });
         tc::Tile wt = t;
         wt.R = walk_R(t, count_slots(dets[c[0]].nring, xr[c[0]].data()));
-        const size_t per_walk = op == TC_OP_FWD ? (size_t)tc::fwd_walk_pairs(wt) : 1;
+        const size_t per_walk = (size_t)(op == TC_OP_FWD ? tc::fwd_walk_pairs(wt) : tc::adj_walk_pairs_of(wt));
         for (size_t k = 0; k < c.size(); k += per_walk)
             walks.push_back({std::vector<int>(c.begin() + k, c.begin() + std::min(c.size(), k + per_walk)), wt});
     }
@@ -1225,6 +1227,14 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         sym_off[i] = off;
         off = align_up(off + sizeof(int) * (size_t)(2 * dets[i].mbmax + 1));
     }
+    // adjoint: the U and V rows of a walk's later members (the first uses its walk's layout)
+    std::vector<size_t> uv_off(ndet, 0);
+    for (int w = 0; w < nwalk && op == TC_OP_ADJ; ++w)
+        for (size_t q = 1; q < walks[w].mem.size(); ++q) {
+            const int i = walks[w].mem[q];
+            uv_off[i] = off;
+            off = align_up(off + 2 * align_up((size_t)16 * (size_t)(2 * dets[i].mbmax + 1) * (size_t)lay[w].P));
+        }
     if (nitems > 0x7fffffffLL / 3) { destroy_plan(p); return fail(TC_EUNSUPPORTED, "too many work items"); }
     const size_t args_off = off;
     const size_t args_bytes = op == TC_OP_FWD ? sizeof(tc::FwdArgs) * nwalk : sizeof(tc::AdjArgs) * nwalk;
@@ -1265,12 +1275,13 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         const int* cmb = reinterpret_cast<const int*>(img.data() + L.colmb);
         for (int c = 0; c < L.ncol; ++c) {
             const int len = d.lmax - std::max(std::abs(cmb[c]), cms[c]) + 1;
-            if (op == TC_OP_ADJ) {   // one item walks every ring tile of the column
-                items.push_back({wt.R, w, c, 0, (long long)len * L.nslot});
-                continue;
-            }
             int k = 0;   // members with this column's beam row
             for (int i : mem) k += dets[i].mbmax >= std::abs(cmb[c]);
+            if (op == TC_OP_ADJ) {   // one item walks every ring tile of the column
+                // a step costs about 2 + 5k operations per chain (the recursion, k cotangents' sums)
+                items.push_back({wt.R, w, c, 0, (long long)len * L.nslot * (2 + 5 * k)});
+                continue;
+            }
             for (int t = 0; t < L.ntile; ++t) {
                 const int slots = std::min(wt.NT * wt.R, L.nslot - t * wt.NT * wt.R);
                 // a step costs about 2 + 2k operations per chain (the recursion, k outputs' sums)
@@ -1299,14 +1310,21 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             a.ring = ring_ptrs(ws, L, d.nring);
             a.slots = reinterpret_cast<const int*>(static_cast<char*>(ws) + L.slots);
             a.col = col_ptrs(ws, L);
-            a.Cbar = d.Cbar;
-            a.U = reinterpret_cast<double*>(static_cast<char*>(ws) + L.U);
-            a.V = reinterpret_cast<double*>(static_cast<char*>(ws) + L.V);
             a.P = L.P;
-            tc::EpiArgs& e = ea[mem[0]];
-            e = tc::EpiArgs{};
-            e.lmax = d.lmax; e.mbmax = d.mbmax; e.P = L.P; e.sky_lmax = lmax_sky;
-            e.U = a.U; e.V = a.V; e.alm = alm; e.blm = d.blm; e.alm_bar = nullptr; e.blm_bar = d.blm_bar;
+            a.npair = (int)mem.size();
+            for (size_t q = 0; q < mem.size(); ++q) {
+                const tc_detector& m = dets[mem[q]];
+                char* uv = q == 0 ? static_cast<char*>(ws) + L.U : dm + uv_off[mem[q]];
+                const size_t ubytes = (size_t)16 * (size_t)(2 * m.mbmax + 1) * (size_t)L.P;
+                a.pmbmax[q] = m.mbmax;
+                a.Cbar[q] = m.Cbar;
+                a.U[q] = reinterpret_cast<double*>(uv);
+                a.V[q] = reinterpret_cast<double*>(q == 0 ? static_cast<char*>(ws) + L.V : uv + align_up(ubytes));
+                tc::EpiArgs& e = ea[mem[q]];
+                e = tc::EpiArgs{};
+                e.lmax = m.lmax; e.mbmax = m.mbmax; e.P = L.P; e.sky_lmax = lmax_sky;
+                e.U = a.U[q]; e.V = a.V[q]; e.alm = alm; e.blm = m.blm; e.alm_bar = nullptr; e.blm_bar = m.blm_bar;
+            }
         }
     }
     // one launch per R, over its items longest first

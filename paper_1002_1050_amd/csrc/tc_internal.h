@@ -64,14 +64,17 @@ struct FwdArgs {
 };
 
 struct AdjArgs {
-    int lmax, mbmax, nring, nslot, ncol, ntile;
+    int lmax, mbmax, nring, nslot, ncol, ntile;   // mbmax: of the column table (the largest pmbmax)
     int skip_exp;
     RingTables ring;
     const int* slots;
     ColumnTables col;
-    const double* Cbar;    // layout of C
-    double* U;             // complex [2M+1][P] direct-ring sums u_l (all ring tiles of a column)
-    double* V;             // complex [2M+1][P] mirror-ring sums (before the (-1)^(l-msky) sign)
+    int npair;             // cotangents sharing the walk: 1, or the detectors of a batched walk
+                           // (same lmax and rings), ordered by pmbmax, largest first
+    int pmbmax[kMaxPairs]; // rows of cotangent p and of its sums: mb = -pmbmax[p] .. pmbmax[p]
+    const double* Cbar[kMaxPairs];  // layout of C, per cotangent
+    double* U[kMaxPairs];  // complex [2 pmbmax+1][P] direct-ring sums u_l (all ring tiles of a column)
+    double* V[kMaxPairs];  // complex [2 pmbmax+1][P] mirror-ring sums (before the (-1)^(l-msky) sign)
     long long P;           // (L+1)(L+2)/2
 };
 
@@ -126,8 +129,9 @@ int launch_adj_epilogue(const EpiArgs& e, void* stream);
 // Batched launches: one workgroup per item; forward items are (walk, column, ring tile) triples,
 // adjoint items (detector, column) pairs (the workgroup walks every ring tile of the column).
 int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t, void* stream);
-// Detectors one batched forward walk serves with tile t (at most kMaxPairs).
+// Detectors one batched forward / adjoint walk serves with tile t (at most kMaxPairs).
 int fwd_walk_pairs(Tile t);
+int adj_walk_pairs_of(Tile t);
 int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, void* stream);
 int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream);
 int launch_adj_beam(const EpiArgs& e, void* stream);

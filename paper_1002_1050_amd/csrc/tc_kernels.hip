@@ -890,35 +890,39 @@ __device__ __forceinline__ double row_shift_up(double v)
 }
 
 // Emitted row sums: slot (t - 16) mod 2 TB for the sum that leaves lane 15 at time t
-// (l offset t - 15), then (wave, row, component); slots are OUT_STRIDE doubles apart (one
-// more than the 4 NW 4 they hold, so that the reads of the block sum, one slot per lane,
-// spread over the LDS banks).
-template <int NT>
-constexpr int out_stride() { return (NT / 64) * 4 * 4 + 1; }
+// (l offset t - 15), then (wave, row, component); slots are out_stride doubles apart (one
+// more than the NW 4 4 NC they hold, so that the reads of the block sum, one slot per lane,
+// spread over the LDS banks).  NC cotangents share the walk: 4 NC components.
+template <int NT, int NC>
+constexpr int out_stride() { return (NT / 64) * 4 * 4 * NC + 1; }
 
 // The coefficient ring holds four blocks of TB l offsets plus a copy of its first TS
 // slots behind its end, so that the TS consecutive offsets of a step group never wrap.
-template <int NT, int TB>
+// NCMAX: the most cotangents a walk in this workgroup serves.
+template <int NT, int TB, int NCMAX>
 struct AdjShared {
     double2 cfa[4 * TB + TS];                     // {A', nB'} per l offset, slot = offset mod 4 TB
     double cic[4 * TB + TS];                      // 1 / c_l per l offset (the copy is not read)
-    double out[2 * TB * out_stride<NT>()];        // emitted row sums
+    double out[2 * TB * out_stride<NT, NCMAX>()]; // emitted row sums
     double carry[2];                              // normalisation carry between blocks
 };
 
-template <int NT, int TB>
-constexpr size_t adj_lds_bytes() { return sizeof(AdjShared<NT, TB>); }
+template <int NT, int TB, int NCMAX>
+constexpr size_t adj_lds_bytes() { return sizeof(AdjShared<NT, TB, NCMAX>); }
 
-template <int R, int NT, int TB, int TR>
-__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT, TB>& sh_)
+// One ring tile of column ci for the cotangents 0 .. NC - 1 of the walk (a.Cbar[c], sums into
+// a.U[c], a.V[c], rows of cotangent c offset by a.pmbmax[c]).
+template <int R, int NT, int TB, int NC, int NCMAX>
+__device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, AdjShared<NT, TB, NCMAX>& sh_)
 {
     static_assert(TB % TS == 0 && TS % 2 == 0 && TB >= ROW, "step groups: pairs of steps, TS per check");
-    static_assert(TB * 4 <= NT, "block sum needs TB*4 threads");
+    static_assert(NC <= NCMAX && NC <= kMaxPairs, "cotangents per walk");
     constexpr int NW = NT / 64;
+    constexpr int NS = 4 * NC;              // running sums per lane: (U re, U im, V re, V im) per cotangent
     constexpr int CF_N = 4 * TB;            // coefficient ring: offset blocks kb-1, kb (read), kb+1 (staged)
     constexpr int CF_MASK = CF_N - 1;
     constexpr int OUT_MASK = 2 * TB - 1;    // emitted sums: windows kb (written) and kb-1 (summed)
-    constexpr int OS = out_stride<NT>();
+    constexpr int OS = out_stride<NT, NC>();
     static_assert((CF_N & CF_MASK) == 0 && (2 * TB & OUT_MASK) == 0 && (SKEW + 1) % TS == 0, "ring sizes");
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -929,18 +933,16 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     const int n = L - l0 + 1;              // l values of a chain
     const SeedShape sh = seed_shape(mb, ms);
     const double lnAh = ldg(a.col.lnA + 2 * ci), lnAl = ldg(a.col.lnA + 2 * ci + 1);
-    const double2* Cbar = reinterpret_cast<const double2*>(a.Cbar);
-    const size_t row_d = ((size_t)(mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
-    const size_t row_m = ((size_t)(-mb + a.mbmax) * (L + 1) + ms) * (size_t)a.nring;
     const int s_base = tile * (NT * R) + tid * R;   // a wave: 64 R consecutive ring slots
 
-    double x[R], d[R], dp[R], g1r[R], g1i[R], g2r[R], g2i[R];
+    double x[R], d[R], dp[R], g1r[NC][R], g1i[NC][R], g2r[NC][R], g2i[NC][R];
     int E[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int s = s_base + r;
         x[r] = 0.0; d[r] = 0.0; dp[r] = 0.0; E[r] = 0;
-        g1r[r] = 0.0; g1i[r] = 0.0; g2r[r] = 0.0; g2i[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { g1r[c][r] = 0.0; g1i[c][r] = 0.0; g2r[c][r] = 0.0; g2i[c][r] = 0.0; }
         if (s < a.nslot) {
             const int j = ldg(a.slots + 2 * s);
             x[r] = ldg(a.ring.x + j);
@@ -948,17 +950,24 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                        ldg(a.ring.lsl + j), d[r], E[r]);
         }
     }
-    // A scaled chain (E < 0, |d| < 2^-900) contributes nothing; its cotangent is
+    // A scaled chain (E < 0, |d| < 2^-900) contributes nothing; its cotangents are
     // loaded when it folds into plain doubles.
     auto load_g = [&](int r) {
         const int s = s_base + r;
         if (s < a.nslot && E[r] == 0) {
             const int jd = ldg(a.slots + 2 * s), jm = ldg(a.slots + 2 * s + 1);
-            const double2 v1 = ldg(Cbar + row_d + jd);
-            g1r[r] = v1.x; g1i[r] = v1.y;
-            if (jm >= 0) {
-                const double2 v2 = ldg(Cbar + row_m + jm);
-                g2r[r] = v2.x; g2i[r] = v2.y;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double2* Cbar = reinterpret_cast<const double2*>(a.Cbar[c]);
+                const int M = a.pmbmax[c];
+                const size_t row_d = ((size_t)(mb + M) * (L + 1) + ms) * (size_t)a.nring;
+                const size_t row_m = ((size_t)(-mb + M) * (L + 1) + ms) * (size_t)a.nring;
+                const double2 v1 = ldg(Cbar + row_d + jd);
+                g1r[c][r] = v1.x; g1i[c][r] = v1.y;
+                if (jm >= 0) {
+                    const double2 v2 = ldg(Cbar + row_m + jm);
+                    g2r[c][r] = v2.x; g2i[c][r] = v2.y;
+                }
             }
         }
     };
@@ -971,10 +980,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     bool acc_on = (a.skip_exp <= 0);    // wave-uniform
     const double thr = hot_threshold(a.skip_exp);
 
-    // one U and one V row per column: ring tile 0 writes them, each later tile (walked after it
-    // by the same workgroup) adds to them
-    double2* U = reinterpret_cast<double2*>(a.U) + (size_t)(mb + a.mbmax) * (size_t)a.P;
-    double2* V = reinterpret_cast<double2*>(a.V) + (size_t)(mb + a.mbmax) * (size_t)a.P;
+    // one U and one V row per column and cotangent: ring tile 0 writes them, each later tile
+    // (walked after it by the same workgroup) adds to them
     const size_t urow = packed_index(L, 0, ms);   // + l
 
     auto stage = [&](int blk) {
@@ -992,31 +999,39 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
     // register sets step by step, so that the two sums a pair of steps completes are both
     // still held after it and one store (a branch: only these lanes take it) serves two steps.
     const bool exit_lane = kr == SKEW;
-    double* const outw = sh_.out + wave * 16 + row * 4;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   // set a: the sums after an odd step
-    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;   // set b: the sums after an even step
+    double* const outw = sh_.out + (wave * 4 + row) * NS;
+    double sa[NS], sb[NS];   // set a: the sums after an odd step; set b: after an even step
+#pragma unroll
+    for (int q = 0; q < NS; ++q) { sa[q] = 0.0; sb[q] = 0.0; }
     auto emit2 = [&](int t) {   // step t completed set b, step t + 1 set a; slots t - 16, t - 15
         if (exit_lane) {
             double* o = outw + ((t - SKEW - 1) & OUT_MASK) * OS;
-            o[0] = b0; o[1] = b1; o[2] = b2; o[3] = b3;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) o[q] = sb[q];
             o = outw + ((t - SKEW) & OUT_MASK) * OS;
-            o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) o[q] = sa[q];
         }
     };
     auto shift_a_to_b = [&]() {
-        b0 = row_shift_up(a0); b1 = row_shift_up(a1); b2 = row_shift_up(a2); b3 = row_shift_up(a3);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sb[q] = row_shift_up(sa[q]);
     };
     auto shift_b_to_a = [&]() {
-        a0 = row_shift_up(b0); a1 = row_shift_up(b1); a2 = row_shift_up(b2); a3 = row_shift_up(b3);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sa[q] = row_shift_up(sb[q]);
     };
-    // one step of the R chains of this lane: coefficients k; the sums s0..s3 take e * Cbar
-    auto step = [&](const double2 k, double& s0, double& s1, double& s2, double& s3) {
+    // one step of the R chains of this lane: coefficients k; the sums s take e * Cbar
+    auto step = [&](const double2 k, double (&s)[NS]) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            s0 = fma(d[r], g1r[r], s0);
-            s1 = fma(d[r], g1i[r], s1);
-            s2 = fma(d[r], g2r[r], s2);
-            s3 = fma(d[r], g2i[r], s3);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                s[4 * c + 0] = fma(d[r], g1r[c][r], s[4 * c + 0]);
+                s[4 * c + 1] = fma(d[r], g1i[c][r], s[4 * c + 1]);
+                s[4 * c + 2] = fma(d[r], g2r[c][r], s[4 * c + 2]);
+                s[4 * c + 3] = fma(d[r], g2i[c][r], s[4 * c + 3]);
+            }
             const double u = fma(x[r], k.x, k.y);
             const double dn = fma(u, d[r], -dp[r]);
             dp[r] = d[r];
@@ -1061,12 +1076,13 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const double dd = (live && acc_on) ? d[r] : 0.0;
-                            if (t & 1) {
-                                a0 = fma(dd, g1r[r], a0); a1 = fma(dd, g1i[r], a1);
-                                a2 = fma(dd, g2r[r], a2); a3 = fma(dd, g2i[r], a3);
-                            } else {
-                                b0 = fma(dd, g1r[r], b0); b1 = fma(dd, g1i[r], b1);
-                                b2 = fma(dd, g2r[r], b2); b3 = fma(dd, g2i[r], b3);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                double* s = (t & 1) ? sa : sb;
+                                s[4 * c + 0] = fma(dd, g1r[c][r], s[4 * c + 0]);
+                                s[4 * c + 1] = fma(dd, g1i[c][r], s[4 * c + 1]);
+                                s[4 * c + 2] = fma(dd, g2r[c][r], s[4 * c + 2]);
+                                s[4 * c + 3] = fma(dd, g2i[c][r], s[4 * c + 3]);
                             }
                             const double u = fma(x[r], k.x, k.y);
                             const double dn = fma(u, d[r], -dp[r]);
@@ -1086,9 +1102,9 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                             kn0 = sh_.cfa[cb + h + 2]; kn1 = sh_.cfa[cb + h + 3];
                         }
                         shift_a_to_b();
-                        step(k0, b0, b1, b2, b3);
+                        step(k0, sb);
                         shift_b_to_a();
-                        step(k1, a0, a1, a2, a3);
+                        step(k1, sa);
                         emit2(t0 + h);
                     }
                 } else {
@@ -1105,7 +1121,8 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                         }
                     }
                     // nothing is added yet: every sum of these steps is zero
-                    a0 = 0.0; a1 = 0.0; a2 = 0.0; a3 = 0.0; b0 = 0.0; b1 = 0.0; b2 = 0.0; b3 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) { sa[q] = 0.0; sb[q] = 0.0; }
 #pragma unroll
                     for (int t = 0; t < TS; t += 2) emit2(t0 + t);
                 }
@@ -1115,15 +1132,23 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
         __syncthreads();
         // window kb: the sums of l offsets kb TB - 15 .. (kb+1) TB - 16, all emitted in this
         // block; the waves and rows in a fixed order (the next block writes the other window)
-        if (tid < TB * 4) {
-            const int o = buf_t - SKEW + (tid >> 2), c = tid & 3;
+        for (int q = tid; q < TB * NS; q += NT) {
+            const int o = buf_t - SKEW + q / NS, comp = q % NS;
             if (o >= 0 && o < n) {
-                const double* src = sh_.out + ((o - 1) & OUT_MASK) * OS + c;
+                const double* src = sh_.out + ((o - 1) & OUT_MASK) * OS + comp;
                 double v = 0.0;
 #pragma unroll
-                for (int w = 0; w < NW * 4; ++w) v += src[4 * w];
+                for (int w = 0; w < NW * 4; ++w) v += src[NS * w];
                 v *= sh_.cic[o & CF_MASK];   // e^l back to d^l
-                double* dst = reinterpret_cast<double*>(c < 2 ? U : V) + 2 * (urow + l0 + o) + (c & 1);
+                const int c = comp >> 2, part = comp & 3;
+                // the cotangent's rows by selection: a runtime index into the argument
+                // record would move the record to scratch memory
+                double* uv = part < 2 ? a.U[0] : a.V[0];
+                int M = a.pmbmax[0];
+#pragma unroll
+                for (int cc = 1; cc < NC; ++cc)
+                    if (c == cc) { uv = part < 2 ? a.U[cc] : a.V[cc]; M = a.pmbmax[cc]; }
+                double* dst = uv + 2 * ((size_t)(mb + M) * (size_t)a.P + urow + l0 + o) + (part & 1);
                 stg(dst, (tile == 0) ? v : ldg(dst) + v);
             }
         }
@@ -1134,32 +1159,58 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
 // column's U and V rows, each later tile adds to them (the same thread writes an element in
 // every tile), so no launch has to wait for another.  The column's values the compiler keeps
 // across tiles spill outside the step loops only.
-template <int R, int NT, int TB, int TR>
-__device__ __forceinline__ void adj_tiles(const AdjArgs& a, int ci, AdjShared<NT, TB>& sh)
+template <int R, int NT, int TB, int NC, int NCMAX>
+__device__ __forceinline__ void adj_tiles(const AdjArgs& a, int ci, AdjShared<NT, TB, NCMAX>& sh)
 {
     for (int tile = 0; tile < a.ntile; ++tile) {
         if (tile > 0) __syncthreads();   // the tile before still reads the LDS ring in its last block sums
-        adj_column<R, NT, TB, TR>(a, ci, tile, sh);
+        adj_column<R, NT, TB, NC, NCMAX>(a, ci, tile, sh);
     }
 }
 
 template <int R, int NT, int TB, int TR>
 __global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj(const AdjArgs a)
 {
-    static_assert(adj_lds_bytes<NT, TB>() * adj_min_waves<R, TB>() <= 160 * 1024, "LDS per CU");
-    __shared__ AdjShared<NT, TB> sh;
-    adj_tiles<R, NT, TB, TR>(a, blockIdx.x, sh);
+    static_assert(adj_lds_bytes<NT, TB, 1>() * adj_min_waves<R, TB>() <= 160 * 1024, "LDS per CU");
+    __shared__ AdjShared<NT, TB, 1> sh;
+    adj_tiles<R, NT, TB, 1, 1>(a, blockIdx.x, sh);
 }
 
-// Batched form: one workgroup per (detector, column) item, the items longest first.
+// Batched form: one workgroup per (walk, column) item, the items longest first.  A walk serves
+// the npair <= adj_walk_pairs<TB>() detectors that share its lmax and rings, ordered by mbmax,
+// largest first: the first k of them have the column's beam row mb, and one walk adds into
+// the sums of all k (2 + 4 k instructions and 4 k / R row shifts per chain step, where k walks
+// of their own take 6 k and 4 k / R).  Two cotangents double the emitted-sum buffer, which
+// with TB 64 would leave one workgroup per CU, and hold 8 cotangent doubles per chain, which
+// at R 8 exceed the 256 registers of two waves per SIMD: paired walks are built with TB 32 and
+// R <= 4 only (two workgroups per CU).
+template <int R, int TB>
+constexpr int adj_walk_pairs() { return (R <= 4 && TB <= 32) ? 2 : 1; }
+
+// Paired walks hold two workgroups per CU (their LDS), which is the register budget they get.
+template <int R, int TB>
+constexpr int adj_items_min_waves() { return adj_walk_pairs<R, TB>() == 2 ? 2 : adj_min_waves<R, TB>(); }
+
 template <int R, int NT, int TB, int TR>
-__global__ void __launch_bounds__(NT, (adj_min_waves<R, TB>())) k_adj_items(const AdjArgs* __restrict__ dets,
+__global__ void __launch_bounds__(NT, (adj_items_min_waves<R, TB>())) k_adj_items(const AdjArgs* __restrict__ dets,
                                                                             const int* __restrict__ items)
 {
-    __shared__ AdjShared<NT, TB> sh;
+    constexpr int K = adj_walk_pairs<R, TB>();
+    static_assert(adj_lds_bytes<NT, TB, K>() * 2 <= 160 * 1024, "two workgroups per CU");
+    __shared__ AdjShared<NT, TB, K> sh;
     const int* item = items + 2 * (size_t)blockIdx.x;
-    const AdjArgs a = dets[item[0]];
-    adj_tiles<R, NT, TB, TR>(a, item[1], sh);
+    const int ci = item[1];
+    if constexpr (K == 2) {
+        // read in place: a copy of the record would sit in scratch memory in this form
+        const AdjArgs& a = dets[item[0]];
+        if (a.npair > 1 && a.pmbmax[1] >= abs(ldg(a.col.mb + ci)))
+            adj_tiles<R, NT, TB, 2, K>(a, ci, sh);
+        else
+            adj_tiles<R, NT, TB, 1, K>(a, ci, sh);
+    } else {
+        const AdjArgs a = dets[item[0]];
+        adj_tiles<R, NT, TB, 1, K>(a, ci, sh);
+    }
 }
 
 // u(mb, ms, l) = U[mb] + (-1)^(l-ms) V[-mb], defined for l >= max(|mb|, ms)
@@ -1381,6 +1432,12 @@ int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t,
 }
 
 int fwd_walk_pairs(Tile t) { return t.R >= 8 ? walk_pairs<8>() : walk_pairs<4>(); }
+
+int adj_walk_pairs_of(Tile t)
+{
+    if (t.TB > 32) return adj_walk_pairs<4, 64>();
+    return t.R >= 8 ? adj_walk_pairs<8, 32>() : adj_walk_pairs<4, 32>();
+}
 
 int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, void* stream)
 {

@@ -223,6 +223,65 @@ def test_batched_adjoint_equals_plain_and_oracle(B, orc):
     assert e <= 1e-11
 
 
+def test_batched_adjoint_shared_walks(B, orc):
+    """At TB 32 and R <= 4 an adjoint walk serves two detectors of one lmax and one ring set (the
+    larger mbmax first; the second adds its sums only for the columns of its own beam rows).
+    Five such detectors with mbmax 9, 6, 4, 2, 0 make walks (9, 6), (4, 2) and (0), two more of
+    another lmax a pair walked at R 2: every beam gradient equals the plain call's at the walk's
+    tile bit for bit, the summed sky gradient the sum of the plain ones, and both the oracle's
+    to 1e-11."""
+    L, x = 90, S.ring_cosines(2500)                  # 1250 ring pairs: two tiles at R 4
+    x2 = S.ring_cosines(301)
+    spec = [(L, 9, x), (L, 6, x), (L, 4, x), (L, 2, x), (L, 0, x), (70, 5, x2), (70, 3, x2)]
+    lsky = 95
+    alm_h = S.sky_alm(lsky, 81) + 0.0j
+    alm = dev(alm_h)
+    dets, blms, Gs = [], [], []
+    for i, (l, m, xr) in enumerate(spec):
+        blm_h = S.random_beam(l, m, 600 + i)
+        G_h = S.random_cbar(l, m, xr.size, 700 + i)
+        blms.append(blm_h)
+        Gs.append(G_h)
+        dets.append({"lmax": l, "mbmax": m, "cosbeta": xr, "blm": dev(blm_h), "Cbar": dev(G_h),
+                     "blm_bar": torch.empty((2 * m + 1, l + 1), dtype=torch.complex128, device="cuda")})
+    alm_bar = torch.empty_like(alm)
+    B.set_tile_ex(B.TC_OP_ADJ, 4, 32, 4)
+    try:
+        say(f"shared-walk adjoint plan, {len(dets)} detectors, tile (4, 32)")
+        plan = B.Plan(B.TC_OP_ADJ, dets, lsky, alm, alm_bar)
+        alm_bar.fill_(float("nan"))
+        for d in dets:
+            d["blm_bar"].fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        plan.close()
+        plains = []
+        for (l, m, xr), d in zip(spec, dets):
+            B.set_tile_ex(B.TC_OP_ADJ, walk_R(4, xr), 32, 4)
+            ga, gb = B.totalconv_adj_x(l, m, xr, dev(truncate_sky(alm_h, lsky, l)), d["blm"], d["Cbar"])
+            plains.append((ga.cpu().numpy(), gb.cpu()))
+    finally:
+        B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
+    sky_sum = np.zeros_like(alm_h)
+    ref_sum = np.zeros_like(alm_h)
+    for i, (l, m, xr) in enumerate(spec):
+        got = dets[i]["blm_bar"].cpu()
+        assert torch.equal(plains[i][1], got), f"detector {i} (lmax {l}, mbmax {m}): batched != plain"
+        a_t = truncate_sky(alm_h, lsky, l)
+        ra, rb = orc.totalconv_adj(l, m, xr, a_t, blms[i], Gs[i])
+        eb = max(np.linalg.norm(got.numpy()[r] - rb[r]) / np.linalg.norm(rb[r])
+                 for r in range(2 * m + 1) if np.any(rb[r] != 0))
+        say(f"  detector {i} (lmax {l}, mbmax {m}): beam gradient vs oracle {eb:.2e}")
+        assert eb <= 1e-11
+        sky_sum += pad_sky(plains[i][0], l, lsky)
+        ref_sum += pad_sky(ra, l, lsky)
+    got = alm_bar.cpu().numpy()
+    assert np.linalg.norm(got - sky_sum) <= 1e-14 * np.linalg.norm(sky_sum)
+    e = np.linalg.norm(got - ref_sum) / np.linalg.norm(ref_sum)
+    say(f"  summed sky gradient vs oracle {e:.2e}")
+    assert e <= 1e-11
+
+
 def test_plan_rejects_bad_detectors(B):
     alm = dev(S.sky_alm(20, 1))
     bad = [{"lmax": 25, "mbmax": 2, "cosbeta": S.ring_cosines(8), "blm": dev(S.random_beam(25, 2, 1)),
