@@ -1256,7 +1256,11 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
     std::vector<tc::FwdArgs> fa(op == TC_OP_FWD ? nwalk : 0);
     std::vector<tc::AdjArgs> aa(op == TC_OP_ADJ ? nwalk : 0);
     std::vector<tc::EpiArgs> ea(ndet);
-    struct Item { int R, walk, col, tile; long long cost; };
+    // Launch groups: the walks of one R (forward), of one R and one lmax (adjoint: each group's
+    // epilogues run beside the next group's walks).
+    struct Group { int R, lmax; tc::Tile tile; long long cost; std::vector<int> walks; };
+    std::vector<Group> groups;
+    struct Item { int grp, walk, col, tile; long long cost; };
     std::vector<Item> items;
     items.reserve((size_t)nitems);
     for (int w = 0; w < nwalk; ++w) {
@@ -1264,6 +1268,11 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         const tc::Tile& wt = walks[w].tile;
         const tc_detector& d = dets[mem[0]];
         const Layout& L = lay[w];
+        const int glmax = op == TC_OP_ADJ ? d.lmax : -1;
+        int grp = 0;
+        while (grp < (int)groups.size() && !(groups[grp].R == wt.R && groups[grp].lmax == glmax)) ++grp;
+        if (grp == (int)groups.size()) groups.push_back({wt.R, glmax, wt, 0, {}});
+        groups[grp].walks.push_back(w);
         std::vector<char> img(L.tables_end, 0);
         build_rings(d.nring, xr[mem[0]].data(), img, L);
         build_slots(d.nring, xr[mem[0]].data(), img, L);
@@ -1279,13 +1288,13 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             for (int i : mem) k += dets[i].mbmax >= std::abs(cmb[c]);
             if (op == TC_OP_ADJ) {   // one item walks every ring tile of the column
                 // a step costs about 2 + 5k operations per chain (the recursion, k cotangents' sums)
-                items.push_back({wt.R, w, c, 0, (long long)len * L.nslot * (2 + 5 * k)});
+                items.push_back({grp, w, c, 0, (long long)len * L.nslot * (2 + 5 * k)});
                 continue;
             }
             for (int t = 0; t < L.ntile; ++t) {
                 const int slots = std::min(wt.NT * wt.R, L.nslot - t * wt.NT * wt.R);
                 // a step costs about 2 + 2k operations per chain (the recursion, k outputs' sums)
-                items.push_back({wt.R, w, c, t, (long long)len * slots * (2 + 2 * k)});
+                items.push_back({grp, w, c, t, (long long)len * slots * (2 + 2 * k)});
             }
         }
         if (op == TC_OP_FWD) {
@@ -1327,21 +1336,24 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
             }
         }
     }
-    // one launch per R, over its items longest first
+    // one launch per group, the costliest group first, each over its items longest first
+    for (const Item& it : items) groups[it.grp].cost += it.cost;
+    std::vector<int> rank(groups.size());
+    {
+        std::vector<int> order(groups.size());
+        for (size_t g = 0; g < groups.size(); ++g) order[g] = (int)g;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return groups[a].cost > groups[b].cost; });
+        for (size_t r = 0; r < order.size(); ++r) rank[order[r]] = (int)r;
+    }
     p->nitems = (int)items.size();
-    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-        return a.R != b.R ? a.R > b.R : a.cost > b.cost;
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+        return rank[a.grp] != rank[b.grp] ? rank[a.grp] < rank[b.grp] : a.cost > b.cost;
     });
-    struct Launch { tc::Tile tile; int first, n; long long cost; };
+    struct Launch { int grp, first, n; };
     std::vector<Launch> launches;
     for (size_t k = 0; k < items.size(); ++k) {
-        if (launches.empty() || launches.back().tile.R != items[k].R) {
-            tc::Tile lt = tile;
-            lt.R = items[k].R;
-            launches.push_back({lt, (int)k, 0, 0});
-        }
+        if (launches.empty() || launches.back().grp != items[k].grp) launches.push_back({items[k].grp, (int)k, 0});
         launches.back().n += 1;
-        launches.back().cost += items[k].cost;
     }
     const int per_item = op == TC_OP_FWD ? 3 : 2;
     std::vector<int> it3((size_t)per_item * items.size());
@@ -1350,74 +1362,80 @@ int tc_plan_create(void** plan, int op, int ndet, const tc_detector* dets, int l
         it3[per_item * k + 1] = items[k].col;
         if (per_item == 3) it3[per_item * k + 2] = items[k].tile;
     }
+    // adjoint: the epilogue records of each launch's detectors, launch by launch
+    std::vector<tc::EpiArgs> eg;
+    std::vector<int> eg_first(launches.size() + 1, 0);
+    for (size_t k = 0; k < launches.size() && op == TC_OP_ADJ; ++k) {
+        eg_first[k] = (int)eg.size();
+        for (int w : groups[launches[k].grp].walks)
+            for (int i : walks[w].mem) eg.push_back(ea[i]);
+    }
+    eg_first[launches.size()] = (int)eg.size();
     rc = (int)hipMemcpy(dm + args_off, op == TC_OP_FWD ? (const void*)fa.data() : (const void*)aa.data(), args_bytes,
                         hipMemcpyHostToDevice);
     if (!rc && op == TC_OP_ADJ)
-        rc = (int)hipMemcpy(dm + epi_off, ea.data(), sizeof(tc::EpiArgs) * ndet, hipMemcpyHostToDevice);
+        rc = (int)hipMemcpy(dm + epi_off, eg.data(), sizeof(tc::EpiArgs) * eg.size(), hipMemcpyHostToDevice);
     if (!rc) rc = (int)hipMemcpy(dm + items_off, it3.data(), sizeof(int) * it3.size(), hipMemcpyHostToDevice);
     if (rc) { destroy_plan(p); return hip_fail(rc, "plan: argument upload"); }
 
-    // ---- capture the graph on a private stream (the caller's stream may be the legacy one).  The
-    // launches of the different R run side by side: the costliest on the capture stream, each other
-    // on a stream of its own forked from it and joined back before the epilogues.  The adjoint's
-    // epilogues (each too small to fill the device) run side by side the same way: the summed sky
-    // gradient on the capture stream, the beam gradients spread over the side streams.
-    int nbeam = 0;
-    for (int i = 0; i < ndet; ++i) nbeam += (op == TC_OP_ADJ && dets[i].blm_bar) ? 1 : 0;
-    const int nside = std::max(launches.empty() ? 0 : (int)launches.size() - 1, std::min(nbeam, 8));
+    // ---- capture the graph on a private stream (the caller's stream may be the legacy one).
+    // Forward: the launches run side by side, the costliest on the capture stream, each other on
+    // a stream of its own forked from it and joined back.  Adjoint: the launches run one after the
+    // other on the capture stream; after each, a second stream runs the epilogues of its
+    // detectors (memory-bound) beside the next launch's walks (ALU-bound): the sky gradient, summed
+    // launch by launch in a fixed order (the first launch writes it, the others add to it), and
+    // each detector's beam gradient.
+    const int nside = op == TC_OP_FWD ? std::max(0, (int)launches.size() - 1) : 1;
+    const int nev = op == TC_OP_FWD ? nside : (int)launches.size() + 1;
     std::vector<hipStream_t> side(nside, nullptr);
-    std::vector<hipEvent_t> joins(nside, nullptr);
-    hipEvent_t fork = nullptr, fork2 = nullptr;
+    std::vector<hipEvent_t> evs(nev, nullptr);
+    hipEvent_t fork = nullptr;
     hipStream_t cs = nullptr;
     auto release_capture = [&] {
         for (hipStream_t q : side) if (q) (void)hipStreamDestroy(q);
-        for (hipEvent_t e : joins) if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : evs) if (e) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
-        if (fork2) (void)hipEventDestroy(fork2);
         if (cs) (void)hipStreamDestroy(cs);
     };
     rc = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (!rc) rc = (int)hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    if (!rc) rc = (int)hipEventCreateWithFlags(&fork2, hipEventDisableTiming);
-    for (int k = 0; k < nside && !rc; ++k) {
-        rc = (int)hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
-        if (!rc) rc = (int)hipEventCreateWithFlags(&joins[k], hipEventDisableTiming);
-    }
+    for (int k = 0; k < nside && !rc; ++k) rc = (int)hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+    for (int k = 0; k < nev && !rc; ++k) rc = (int)hipEventCreateWithFlags(&evs[k], hipEventDisableTiming);
     if (rc) { release_capture(); destroy_plan(p); return hip_fail(rc, "plan: capture streams"); }
-    std::stable_sort(launches.begin(), launches.end(), [](const Launch& a, const Launch& b) { return a.cost > b.cost; });
     rc = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     const int* d_items = reinterpret_cast<const int*>(dm + items_off);
-    for (int i = 0; i < ndet && !rc && op == TC_OP_FWD; ++i)   // beam row signs, on every execution
-        rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax, reinterpret_cast<int*>(dm + sym_off[i]),
-                                      cs);
-    const int nfork = (int)launches.size() - 1;
-    if (!rc && nfork > 0) rc = (int)hipEventRecord(fork, cs);
-    for (size_t k = 0; k < launches.size() && !rc; ++k) {
-        hipStream_t q = k == 0 ? cs : side[k - 1];
-        if (k > 0) rc = (int)hipStreamWaitEvent(q, fork, 0);
-        const Launch& l = launches[k];
-        if (!rc && op == TC_OP_FWD)
-            rc = tc::launch_fwd_items(reinterpret_cast<const tc::FwdArgs*>(dm + args_off), d_items + 3 * (size_t)l.first,
-                                      l.n, l.tile, q);
-        if (!rc && op == TC_OP_ADJ)
-            rc = tc::launch_adj_items(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items + 2 * (size_t)l.first,
-                                      l.n, l.tile, q);
-        if (!rc && k > 0) rc = (int)hipEventRecord(joins[k - 1], q);
-    }
-    for (int k = 0; k < nfork && !rc; ++k) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
-    if (!rc && op == TC_OP_ADJ) {
-        const int nb = std::min(nbeam, nside);   // side streams the beam epilogues take
-        if (nb > 0) rc = (int)hipEventRecord(fork2, cs);
-        for (int k = 0; k < nb && !rc; ++k) rc = (int)hipStreamWaitEvent(side[k], fork2, 0);
-        for (int i = 0, b = 0; i < ndet && !rc; ++i)
-            if (dets[i].blm_bar) rc = tc::launch_adj_beam(ea[i], nb > 0 ? side[b++ % nb] : cs);
-        if (!rc && alm_bar)
-            rc = tc::launch_adj_sky_multi(reinterpret_cast<const tc::EpiArgs*>(dm + epi_off), ndet, lmax_sky, alm_bar,
-                                          cs);
-        for (int k = 0; k < nb && !rc; ++k) {
-            rc = (int)hipEventRecord(joins[k], side[k]);
-            if (!rc) rc = (int)hipStreamWaitEvent(cs, joins[k], 0);
+    if (op == TC_OP_FWD) {
+        for (int i = 0; i < ndet && !rc; ++i)   // beam row signs, on every execution
+            rc = tc::launch_beam_symmetry(dets[i].blm, dets[i].lmax, dets[i].mbmax,
+                                          reinterpret_cast<int*>(dm + sym_off[i]), cs);
+        if (!rc && nside > 0) rc = (int)hipEventRecord(fork, cs);
+        for (size_t k = 0; k < launches.size() && !rc; ++k) {
+            hipStream_t q = k == 0 ? cs : side[k - 1];
+            if (k > 0) rc = (int)hipStreamWaitEvent(q, fork, 0);
+            const Launch& l = launches[k];
+            if (!rc)
+                rc = tc::launch_fwd_items(reinterpret_cast<const tc::FwdArgs*>(dm + args_off),
+                                          d_items + 3 * (size_t)l.first, l.n, groups[l.grp].tile, q);
+            if (!rc && k > 0) rc = (int)hipEventRecord(evs[k - 1], q);
         }
+        for (int k = 0; k < nside && !rc; ++k) rc = (int)hipStreamWaitEvent(cs, evs[k], 0);
+    } else {
+        hipStream_t es = side[0];
+        const tc::EpiArgs* d_eg = reinterpret_cast<const tc::EpiArgs*>(dm + epi_off);
+        for (size_t k = 0; k < launches.size() && !rc; ++k) {
+            const Launch& l = launches[k];
+            rc = tc::launch_adj_items(reinterpret_cast<const tc::AdjArgs*>(dm + args_off), d_items + 2 * (size_t)l.first,
+                                      l.n, groups[l.grp].tile, cs);
+            if (!rc) rc = (int)hipEventRecord(evs[k], cs);
+            if (!rc) rc = (int)hipStreamWaitEvent(es, evs[k], 0);
+            if (!rc && alm_bar)
+                rc = tc::launch_adj_sky_multi(d_eg + eg_first[k], eg_first[k + 1] - eg_first[k], lmax_sky, k > 0,
+                                              alm_bar, es);
+            for (int e = eg_first[k]; e < eg_first[k + 1] && !rc; ++e)
+                if (eg[e].blm_bar) rc = tc::launch_adj_beam(eg[e], es);
+        }
+        if (!rc) rc = (int)hipEventRecord(evs[launches.size()], es);
+        if (!rc) rc = (int)hipStreamWaitEvent(cs, evs[launches.size()], 0);
     }
     hipGraph_t g = nullptr;
     const int rc_end = (int)hipStreamEndCapture(cs, &g);

@@ -133,7 +133,8 @@ int launch_fwd_items(const FwdArgs* walks, const int* items, int nitems, Tile t,
 int fwd_walk_pairs(Tile t);
 int adj_walk_pairs_of(Tile t);
 int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, void* stream);
-int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream);
+int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, bool accumulate, double* alm_bar,
+                         void* stream);
 int launch_adj_beam(const EpiArgs& e, void* stream);
 bool tile_supported(int op, Tile t);
 

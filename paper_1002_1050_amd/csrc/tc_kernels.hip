@@ -1216,23 +1216,42 @@ __global__ void __launch_bounds__(NT, (adj_items_min_waves<R, TB>())) k_adj_item
 // u(mb, ms, l) = U[mb] + (-1)^(l-ms) V[-mb], defined for l >= max(|mb|, ms)
 __device__ __forceinline__ double2 u_value(const EpiArgs& e, int mb, int ms, int l, size_t k)
 {
-    const double2 a = reinterpret_cast<const double2*>(e.U)[(size_t)(mb + e.mbmax) * e.P + k];
-    const double2 b = reinterpret_cast<const double2*>(e.V)[(size_t)(-mb + e.mbmax) * e.P + k];
+    const double2 a = ldg(reinterpret_cast<const double2*>(e.U) + (size_t)(mb + e.mbmax) * e.P + k);
+    const double2 b = ldg(reinterpret_cast<const double2*>(e.V) + (size_t)(-mb + e.mbmax) * e.P + k);
     const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
     return make_double2(a.x + sg * b.x, a.y + sg * b.y);
 }
 
-// Adds sum_mb b_{l,mb} u(mb, ms, l) of one detector to (ar, ai).
+// Adds sum_mb b_{l,mb} u(mb, ms, l) of one detector to (ar, ai), mb ascending.  The rows are
+// read SKY_ROWS at a time before any is used, so that a thread keeps that many row loads in
+// flight instead of one.
+constexpr int SKY_ROWS = 8;
 __device__ __forceinline__ void sky_grad_terms(const EpiArgs& e, int ms, int l, double& ar, double& ai)
 {
     const size_t k = packed_index(e.lmax, l, ms);
-    const double2* blm = reinterpret_cast<const double2*>(e.blm);
-    for (int mb = -e.mbmax; mb <= e.mbmax; ++mb) {
-        if (l < abs(mb)) continue;
-        const double2 u = u_value(e, mb, ms, l, k);
-        const double2 b = blm[(size_t)(mb + e.mbmax) * (e.lmax + 1) + l];
-        ar += b.x * u.x - b.y * u.y;
-        ai += b.x * u.y + b.y * u.x;
+    const double2* U = reinterpret_cast<const double2*>(e.U) + k;
+    const double2* V = reinterpret_cast<const double2*>(e.V) + k;
+    const double2* blm = reinterpret_cast<const double2*>(e.blm) + l;
+    const int M = e.mbmax, lo = max(-M, -l), hi = min(M, l);   // rows with l >= |mb|
+    const double sg = ((l - ms) & 1) ? -1.0 : 1.0;
+    for (int mb0 = lo; mb0 <= hi; mb0 += SKY_ROWS) {
+        double2 ua[SKY_ROWS], va[SKY_ROWS], ba[SKY_ROWS];
+#pragma unroll
+        for (int q = 0; q < SKY_ROWS; ++q) {
+            const int mb = min(mb0 + q, hi);   // past the last row: a repeat of it, not added
+            ua[q] = ldg(U + (size_t)(mb + M) * e.P);
+            va[q] = ldg(V + (size_t)(-mb + M) * e.P);
+            ba[q] = ldg(blm + (size_t)(mb + M) * (e.lmax + 1));
+        }
+#pragma unroll
+        for (int q = 0; q < SKY_ROWS; ++q) {
+            if (mb0 + q <= hi) {
+                const double2 u = make_double2(ua[q].x + sg * va[q].x, ua[q].y + sg * va[q].y);
+                const double2 b = ba[q];
+                ar += b.x * u.x - b.y * u.y;
+                ai += b.x * u.y + b.y * u.x;
+            }
+        }
     }
 }
 
@@ -1244,25 +1263,32 @@ __global__ void __launch_bounds__(256) k_adj_sky(const EpiArgs e)
     if (l > e.sky_lmax) return;
     double ar = 0.0, ai = 0.0;
     if (l <= e.lmax) sky_grad_terms(e, ms, l, ar, ai);
-    reinterpret_cast<double2*>(e.alm_bar)[packed_index(e.sky_lmax, l, ms)] = make_double2(ar, ai);
+    stg(reinterpret_cast<double2*>(e.alm_bar) + packed_index(e.sky_lmax, l, ms), make_double2(ar, ai));
 }
 
-// Batched form: the sky gradient sums every detector in a fixed order.
+// Batched form: the sky gradient of ndet detectors, summed in their order; with accumulate the
+// sum is added to what alm_bar holds (the detectors of earlier launches), else it replaces it.
 __global__ void __launch_bounds__(256) k_adj_sky_multi(const EpiArgs* __restrict__ eps, int ndet, int sky_lmax,
-                                                       double* __restrict__ alm_bar)
+                                                       int accumulate, double* __restrict__ alm_bar)
 {
     const int ms = blockIdx.y;
     const int l = ms + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > sky_lmax) return;
+    double2* out = reinterpret_cast<double2*>(alm_bar) + packed_index(sky_lmax, l, ms);
     double ar = 0.0, ai = 0.0;
-    for (int dt = 0; dt < ndet; ++dt) {
-        const EpiArgs e = eps[dt];
-        if (l <= e.lmax && ms <= e.lmax) sky_grad_terms(e, ms, l, ar, ai);
+    if (accumulate) {
+        const double2 o = ldg(out);
+        ar = o.x;
+        ai = o.y;
     }
-    reinterpret_cast<double2*>(alm_bar)[packed_index(sky_lmax, l, ms)] = make_double2(ar, ai);
+    for (int dt = 0; dt < ndet; ++dt) {
+        const EpiArgs& e = eps[dt];
+        if (l <= e.lmax) sky_grad_terms(e, ms, l, ar, ai);
+    }
+    stg(out, make_double2(ar, ai));
 }
 
-// blm_bar_{l,mb} = sum_{ms <= l} s_{l,ms} conj(u(mb, ms, l))
+// blm_bar_{l,mb} = sum_{ms <= l} s_{l,ms} conj(u(mb, ms, l)), one thread per (l, mb)
 __global__ void __launch_bounds__(256) k_adj_beam(const EpiArgs e)
 {
     const int mb = (int)blockIdx.y - e.mbmax;
@@ -1270,7 +1296,7 @@ __global__ void __launch_bounds__(256) k_adj_beam(const EpiArgs e)
     if (l > e.lmax) return;
     double2* out = reinterpret_cast<double2*>(e.blm_bar) + (size_t)(mb + e.mbmax) * (e.lmax + 1) + l;
     if (l < abs(mb)) {
-        *out = make_double2(0.0, 0.0);
+        stg(out, make_double2(0.0, 0.0));
         return;
     }
     const double2* alm = reinterpret_cast<const double2*>(e.alm);
@@ -1278,11 +1304,11 @@ __global__ void __launch_bounds__(256) k_adj_beam(const EpiArgs e)
 #pragma unroll 4
     for (int ms = 0; ms <= l; ++ms) {
         const double2 u = u_value(e, mb, ms, l, packed_index(e.lmax, l, ms));
-        const double2 s = alm[packed_index(e.sky_lmax, l, ms)];
+        const double2 s = ldg(alm + packed_index(e.sky_lmax, l, ms));
         br += s.x * u.x + s.y * u.y;
         bi += s.y * u.x - s.x * u.y;
     }
-    *out = make_double2(br, bi);
+    stg(out, make_double2(br, bi));
 }
 
 template <typename Args>
@@ -1400,12 +1426,7 @@ int launch_adj_epilogue(const EpiArgs& e, void* stream)
         const int rc = (int)hipGetLastError();
         if (rc) return rc;
     }
-    if (e.blm_bar) {
-        dim3 grid((e.lmax + 1 + nt - 1) / nt, 2 * e.mbmax + 1);
-        hipLaunchKernelGGL(k_adj_beam, grid, dim3(nt), 0, (hipStream_t)stream, e);
-        const int rc = (int)hipGetLastError();
-        if (rc) return rc;
-    }
+    if (e.blm_bar) return launch_adj_beam(e, stream);
     return 0;
 }
 
@@ -1453,11 +1474,12 @@ int launch_adj_items(const AdjArgs* dets, const int* items, int nitems, Tile t, 
     return (int)hipErrorInvalidValue;
 }
 
-int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, double* alm_bar, void* stream)
+int launch_adj_sky_multi(const EpiArgs* eps, int ndet, int sky_lmax, bool accumulate, double* alm_bar, void* stream)
 {
     const int nt = 256;
     dim3 grid((sky_lmax + 1 + nt - 1) / nt, sky_lmax + 1);
-    hipLaunchKernelGGL(k_adj_sky_multi, grid, dim3(nt), 0, (hipStream_t)stream, eps, ndet, sky_lmax, alm_bar);
+    hipLaunchKernelGGL(k_adj_sky_multi, grid, dim3(nt), 0, (hipStream_t)stream, eps, ndet, sky_lmax,
+                       accumulate ? 1 : 0, alm_bar);
     return (int)hipGetLastError();
 }
 

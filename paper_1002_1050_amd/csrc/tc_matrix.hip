@@ -27,8 +27,6 @@ namespace tc {
 namespace {
 
 constexpr int MS_TS = 8;          // steps between scale checks
-constexpr int MS_FL = 64;         // steps per flush of the row-gathered images (512-byte row segments)
-constexpr int MS_TB = 64;         // steps per staged coefficient block
 constexpr int MS_FOLD = -900;     // scaled values fold into plain doubles at 2^-900
 
 __device__ __forceinline__ bool wave_any_m(bool p) { return __ballot(p) != 0ull; }

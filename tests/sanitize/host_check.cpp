@@ -26,7 +26,7 @@ int launch_fwd_items(const FwdArgs*, const int*, int, Tile, void*) { return kNoK
 int fwd_walk_pairs(Tile t) { return t.R >= 8 ? 2 : 4; }
 int adj_walk_pairs_of(Tile t) { return (t.R <= 4 && t.TB <= 32) ? 2 : 1; }
 int launch_adj_items(const AdjArgs*, const int*, int, Tile, void*) { return kNoKernel; }
-int launch_adj_sky_multi(const EpiArgs*, int, int, double*, void*) { return kNoKernel; }
+int launch_adj_sky_multi(const EpiArgs*, int, int, bool, double*, void*) { return kNoKernel; }
 int launch_adj_beam(const EpiArgs&, void*) { return kNoKernel; }
 bool tile_supported(int, Tile) { return false; }
 }  // namespace tc
