@@ -67,15 +67,14 @@ def _bytes(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib=2097152.0):
 
 
 MEASURED_TRAFFIC = {
-    # taken on the first source; the second differs from it in one comment only (its
-    # generated device code is identical, instruction for instruction)
-    "kernel_source_sha256": ["5d6d67dd378035359a59db156c0ad53500ff8bee36b5a7d1cade008506d19779",
-                             "64f0e0ad30f0871c75e47fe3364111c427d2a6996d6dfaa810bcc8f34aefdb58"],
+    # FETCH_SIZE and WRITE_SIZE of the kernels as built from this source, each scaled by the
+    # counts of a 2 GiB device-to-device copy in the same run
+    "kernel_source_sha256": ["a4d81153bb5f5256c1b5cf9d088c26cc44a464b3cc362174b67b9fce2d637a34"],
     "lmax4096": {
         # the forward: its two launches, k_fwd_rows and k_fwd, together
-        "k_fwd": {"8,64,4": _bytes(1324193.625 + 3725.5, 15733765.5625 + 0.0, 1048611.625),
-                  "4,64,4": _bytes(973444.5 + 3725.5, 16633937.875 + 0.0, 1048611.625)},
-        "k_adj": {"8,64,4": _bytes(11282825.0625, 18045186.5625, 1048611.625)},
+        "k_fwd": {"8,64,4": _bytes(1372108.9 + 3725.5, 15673236.5 + 0.0, 1048609.9),
+                  "4,64,4": _bytes(973657.8 + 3725.5, 16633838.3 + 0.0, 1048609.9)},
+        "k_adj": {"8,64,4": _bytes(10846246.4, 17289241.8, 1048609.9)},
     },
 }
 

@@ -316,13 +316,19 @@ int tc_get_tile_ex(int op, int lmax, int* R, int* TB, int* TR);
  * Batched plan: many detectors -- each with its own beam, mbmax, lmax and ring
  * set -- convolved with one shared sky, all captured in one HIP graph (the
  * batching is not in the paper).  Detectors with the same lmax and the same ring
- * cosines share walks of the recursion in the forward (up to four per walk, the
- * largest mbmax first; one even / odd walk feeds every member's output, as the
- * polarised pairs of Sec. 4.1's footnote share theirs); one workgroup per work
- * item (walk or detector, column, ring tile), the items longest first; one launch
- * per chains-per-lane R, the launches of different R on parallel graph branches.
- * Every output equals what totalconv_fwd / totalconv_adj computes for that
- * detector at the R the plan walks it with, bit for bit.
+ * cosines share walks of the recursion (largest mbmax first, as the polarised
+ * pairs of Sec. 4.1's footnote share theirs): in the forward up to four per walk
+ * (two at R 8), one even / odd walk feeding every member's output; in the
+ * adjoint two per walk at TB 32 and R <= 4 (at R 8 the second detector's
+ * cotangents do not fit the registers), one walk adding into both detectors'
+ * sums.  One workgroup per work item (walk, column, ring tile), the items
+ * longest first.  Forward: one launch per chains-per-lane R, the launches of
+ * different R on parallel graph branches.  Adjoint: one launch per (R, lmax)
+ * group, the groups one after the other; after each, a second stream runs its
+ * detectors' beam gradients and adds their sky gradients to alm_bar (always in
+ * the same order) beside the next group's walks.  Every beam gradient and forward
+ * output equals what totalconv_fwd / totalconv_adj computes for that detector at
+ * the tile the plan walks it with, bit for bit.
  */
 typedef struct tc_detector {
     int lmax;                /* 0 <= mbmax <= lmax <= lmax_sky                     */
