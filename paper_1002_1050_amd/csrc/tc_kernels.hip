@@ -94,7 +94,7 @@ constexpr int fwd_min_waves() { return NC == 1 ? min_waves<R>() : (R >= 4 ? 2 : 
 template <int R>
 constexpr int rows_min_waves() { return R >= 8 ? 2 : 4; }
 
-// The adjoint's LDS (about 37 KB per workgroup with TB = 32, 73 KB with TB = 64; mostly
+// The adjoint's LDS (about 37 KB per workgroup with TB = 32, 74 KB with TB = 64; mostly
 // the emitted row sums of two blocks) caps residency at 4 or 2 workgroups (waves per
 // SIMD) per CU.
 template <int R, int TB>
@@ -890,11 +890,13 @@ __device__ __forceinline__ double row_shift_up(double v)
 }
 
 // Emitted row sums: slot (t - 16) mod 2 TB for the sum that leaves lane 15 at time t
-// (l offset t - 15), then (wave, row, component); slots are out_stride doubles apart (one
-// more than the NW 4 4 NC they hold, so that the reads of the block sum, one slot per lane,
-// spread over the LDS banks).  NC cotangents share the walk: 4 NC components.
+// (l offset t - 15), then (wave, row, component); slots are out_stride doubles apart: two more
+// than the NW 4 4 NC they hold, an even count, so that every slot is 16-byte aligned and a step
+// group's emissions are 128-bit stores at constant offsets from one address (the reads of the
+// block sum, one slot per lane, then meet at most two to a bank).  NC cotangents share the walk:
+// 4 NC components.
 template <int NT, int NC>
-constexpr int out_stride() { return (NT / 64) * 4 * 4 * NC + 1; }
+constexpr int out_stride() { return (NT / 64) * 4 * 4 * NC + 2; }
 
 // The coefficient ring holds four blocks of TB l offsets plus a copy of its first TS
 // slots behind its end, so that the TS consecutive offsets of a step group never wrap.
@@ -1013,6 +1015,20 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
             for (int q = 0; q < NS; ++q) o[q] = sa[q];
         }
     };
+    // The same for step t0 + h of a step group that starts at t0, a multiple of TS: the group's
+    // slots t0 - 16 .. t0 - 16 + TS - 1 do not wrap the ring (t0 - 16 is a multiple of TS too), so
+    // they are og (the group's first slot, one address per group) plus constant offsets.
+    static_assert((SKEW + 1) % TS == 0 && (2 * TB) % TS == 0, "a step group's slots do not wrap");
+    auto emit2_in = [&](double* og, int h) {
+        if (exit_lane) {
+            double* o = og + h * OS;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) o[q] = sb[q];
+            o = og + (h + 1) * OS;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) o[q] = sa[q];
+        }
+    };
     auto shift_a_to_b = [&]() {
 #pragma unroll
         for (int q = 0; q < NS; ++q) sb[q] = row_shift_up(sa[q]);
@@ -1094,6 +1110,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                 } else if (acc_on) {
                     // pairs of steps; each pair's coefficients are read during the pair before
                     const int cb = (t0 - kr) & CF_MASK;
+                    double* const og = outw + ((t0 - SKEW - 1) & OUT_MASK) * OS;
                     double2 kn0 = sh_.cfa[cb], kn1 = sh_.cfa[cb + 1];
 #pragma unroll
                     for (int h = 0; h < TS; h += 2) {
@@ -1105,7 +1122,7 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                         step(k0, sb);
                         shift_b_to_a();
                         step(k1, sa);
-                        emit2(t0 + h);
+                        emit2_in(og, h);
                     }
                 } else {
                     const int cb = (t0 - kr) & CF_MASK;
@@ -1123,8 +1140,9 @@ __device__ __forceinline__ void adj_column(const AdjArgs& a, int ci, int tile, A
                     // nothing is added yet: every sum of these steps is zero
 #pragma unroll
                     for (int q = 0; q < NS; ++q) { sa[q] = 0.0; sb[q] = 0.0; }
+                    double* const og = outw + ((t0 - SKEW - 1) & OUT_MASK) * OS;
 #pragma unroll
-                    for (int t = 0; t < TS; t += 2) emit2(t0 + t);
+                    for (int t = 0; t < TS; t += 2) emit2_in(og, t);
                 }
             }
         }
