@@ -351,6 +351,64 @@ def _batched16_check(B, orc, w, alm_h, alm, dets, blms):
     assert worst <= 1e-11
 
 
+def test_batched16_adjoint_full_size(B, orc):
+    """The sixteen-detector adjoint plan at full size, at the tile the benchmark's autotuning picks
+    ((8, 64, 4): the lmax 4096 and 2048 detectors walk at R 8, the smaller ones at their own R, in
+    four launch groups with the epilogues of each beside the next), seeded Gaussian cotangents:
+    every beam gradient equals the plain call's at the walk's tile bit for bit, the summed sky
+    gradient equals the sum of the plain calls' to rounding (it is summed group by group), and the
+    smallest detector's gradients (lmax 512, mbmax 4) match the oracle to 1e-11."""
+    w = S.WORKLOADS["batched16"]
+    alm_h = S.sky_alm(w.lmax, w.sky_seed) + 0.0j
+    alm = dev(alm_h)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1617)
+    dets = []
+    for d in w.detectors:
+        dets.append({"lmax": d.lmax, "mbmax": d.mbmax, "cosbeta": d.xring(), "blm": dev(d.blm()),
+                     "Cbar": torch.randn((2 * d.mbmax + 1, d.lmax + 1, d.nring), dtype=torch.complex128,
+                                         device="cuda", generator=g),
+                     "blm_bar": torch.empty((2 * d.mbmax + 1, d.lmax + 1), dtype=torch.complex128,
+                                            device="cuda")})
+    alm_bar = torch.empty_like(alm)
+    B.set_tile_ex(B.TC_OP_ADJ, 8, 64, 4)
+    try:
+        say(f"batched16 adjoint plan at full size, {len(dets)} detectors, tile (8, 64, 4)")
+        plan = B.Plan(B.TC_OP_ADJ, dets, w.lmax, alm, alm_bar)
+        alm_bar.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        plan.close()
+        sky_sum = np.zeros_like(alm_h)
+        small = None
+        for i, (d, det) in enumerate(zip(w.detectors, dets)):
+            L, M, x = d.lmax, d.mbmax, det["cosbeta"]
+            a_t = truncate_sky(alm_h, w.lmax, L)
+            B.set_tile_ex(B.TC_OP_ADJ, walk_R(8, x), 64, 4)
+            ga, gb = B.totalconv_adj_x(L, M, x, dev(a_t), det["blm"], det["Cbar"])
+            assert torch.equal(gb, det["blm_bar"]), f"detector {i} (lmax {L}, mbmax {M}): beam gradient batched != plain"
+            ga_h = ga.cpu().numpy()
+            sky_sum += pad_sky(ga_h, L, w.lmax)
+            if L == 512 and M == 4:
+                small = (i, L, M, x, a_t, det["blm"].cpu().numpy(), det["Cbar"].cpu().numpy(), ga_h,
+                         gb.cpu().numpy())
+            del ga, gb
+            det["Cbar"] = None
+            torch.cuda.empty_cache()
+    finally:
+        B.set_tile_ex(B.TC_OP_ADJ, 0, 0, 0)
+    got = alm_bar.cpu().numpy()
+    e_sum = np.linalg.norm(got - sky_sum) / np.linalg.norm(sky_sum)
+    say(f"  summed sky gradient vs the plain calls' sum {e_sum:.2e}")
+    assert e_sum <= 1e-13
+    i, L, M, x, a_t, blm_h, G_h, ga_h, gb_h = small
+    ra, rb = orc.totalconv_adj(L, M, x, a_t, blm_h, G_h)
+    ea = np.linalg.norm(ga_h - ra) / np.linalg.norm(ra)
+    eb = max(np.linalg.norm(gb_h[r] - rb[r]) / np.linalg.norm(rb[r]) for r in range(2 * M + 1) if np.any(rb[r] != 0))
+    say(f"  detector {i} (lmax {L}, mbmax {M}) vs oracle: sky gradient {ea:.2e}, beam rows {eb:.2e}")
+    assert ea <= 1e-11 and eb <= 1e-11
+
+
 @pytest.mark.parametrize("first", ["sym", "gen"])
 def test_plan_follows_beams_changed_between_executions(B, first):
     """Beams edited in place between executions of one plan.  The two detectors share a walk; the
