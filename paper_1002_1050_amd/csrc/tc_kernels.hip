@@ -583,17 +583,38 @@ __device__ __forceinline__ void fwd_steps_rows(const double4 (*cf)[NS], int s0,
                                                double (&p0r)[NC][R], double (&p0i)[NC][R],
                                                double (&p1r)[NC][R], double (&p1i)[NC][R])
 {
+    // With one output, each step's coefficients and weights are read during the step before (more
+    // outputs leave no registers for it: their walks read them at the step).
+    constexpr bool AHEAD = NC == 1;
+    constexpr int NV = ACC ? (NC + 1) / 2 : 0;
+    double4 kn;
+    double4 vn[NV > 0 ? NV : 1];
+    if constexpr (AHEAD) {
+        kn = cf[s0][0];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) vn[c] = cf[s0][1 + c];
+    }
 #pragma unroll
     for (int t = 0; t < TS; ++t) {
-        const double4 k = cf[s0 + t][0];
+        if constexpr (!AHEAD) {
+            kn = cf[s0 + t][0];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) vn[c] = cf[s0 + t][1 + c];
+        }
+        const double4 k = kn;
         double wr[NC], wi[NC];
         if (ACC) {
 #pragma unroll
             for (int c = 0; c < NC; c += 2) {
-                const double4 v = cf[s0 + t][1 + c / 2];
+                const double4 v = vn[c / 2];
                 wr[c] = v.x; wi[c] = v.y;
                 if (c + 1 < NC) { wr[c + 1] = v.z; wi[c + 1] = v.w; }
             }
+        }
+        if (AHEAD && t + 1 < TS) {
+            kn = cf[s0 + t + 1][0];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) vn[c] = cf[s0 + t + 1][1 + c];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
