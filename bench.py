@@ -69,12 +69,12 @@ def _bytes(fetch_kib, write_kib, copy_fetch_kib, copy_write_kib=2097152.0):
 MEASURED_TRAFFIC = {
     # FETCH_SIZE and WRITE_SIZE of the kernels as built from this source, each scaled by the
     # counts of a 2 GiB device-to-device copy in the same run
-    "kernel_source_sha256": ["68771334f795c6614fe2c7595faba6a45c94f75c037b6a8733c89344a13a5e13"],
+    "kernel_source_sha256": ["accdb2a8b4aad6c420f4213ccefc993ad46b38da8747be5129beade2de1ad0ee"],
     "lmax4096": {
         # the forward: its two launches, k_fwd_rows and k_fwd, together
-        "k_fwd": {"8,64,4": _bytes(1339746.8 + 3725.5, 15714517.0 + 0.0, 1048610.1),
-                  "4,64,4": _bytes(973256.8 + 3726.5, 16634030.4 + 0.0, 1048610.1)},
-        "k_adj": {"8,64,4": _bytes(11087354.1, 17801196.5, 1048610.1)},
+        "k_fwd": {"8,64,4": _bytes(1449012.8 + 3725.5, 16475947.9 + 0.0, 1048611.6),
+                  "4,64,4": _bytes(973078.5 + 3726.5, 16633820.6 + 0.0, 1048611.6)},
+        "k_adj": {"8,64,4": _bytes(11091143.9, 17801268.9, 1048611.6)},
     },
 }
 
