@@ -241,7 +241,9 @@ int totalconv_fwd_pol_x(int lmax, int mbmax, int nring, const double* cosbeta, i
  * alm_bar, blm_bar: (host) arrays of npair device pointers (entries may be
  * NULL; either array may be NULL) receiving the gradients of pair p, as
  * totalconv_adj gives them for that pair's sky, beam and cotangent.  In
- * TC_POL_SUM mode the pairs share one reduction over the rings; in
+ * TC_POL_SUM mode the pairs share one reduction over the rings and one launch
+ * forms every pair's sky gradient from it (each equal, bit for bit, to what
+ * totalconv_adj returns for that pair and the one cotangent); in
  * TC_POL_SEPARATE mode the cotangents are reduced one after the other.
  *   workspace    at least totalconv_workspace_bytes(TC_OP_ADJ, lmax, mbmax, nring) bytes
  */

@@ -1,7 +1,7 @@
 """Build libtotalconv.so in-tree for gfx950.
 
-hipcc compiles the kernels (tc_kernels.hip, tc_cube.hip, tc_matrix.hip) and the no-allocation
-forward's static device array with its entry point (tc_noalloc.hip); the host-side tables and C entry
+hipcc compiles the kernels (tc_kernels.hip, tc_cube.hip, tc_matrix.hip, tc_epilogue.hip) and the
+no-allocation forward's static device array with its entry point (tc_noalloc.hip); the host-side tables and C entry
 points (tc_host.cpp) are plain C++ built with g++ against the HIP runtime
 headers; hipcc links both into paper_1002_1050_amd/libtotalconv.so.
 """
@@ -44,15 +44,17 @@ def build(verbose: bool = True) -> str:
     c_obj = os.path.join(BUILD, "tc_cube.o")
     m_obj = os.path.join(BUILD, "tc_matrix.o")
     n_obj = os.path.join(BUILD, "tc_noalloc.o")
+    e_obj = os.path.join(BUILD, "tc_epilogue.o")
     h_obj = os.path.join(BUILD, "tc_host.o")
     _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_kernels.hip"), "-o", k_obj])
     _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_cube.hip"), "-o", c_obj])
     _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_matrix.hip"), "-o", m_obj])
     _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_noalloc.hip"), "-o", n_obj])
+    _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tc_epilogue.hip"), "-o", e_obj])
     _run(["g++", "-O2", "-fPIC", "-std=c++17", "-Wall", "-D__HIP_PLATFORM_AMD__",
           "-I", os.path.join(ROCM, "include"), *inc, "-c", os.path.join(CSRC, "tc_host.cpp"), "-o", h_obj])
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, c_obj, m_obj, n_obj, h_obj,
+    _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, c_obj, m_obj, n_obj, e_obj, h_obj,
           "-L", os.path.join(ROCM, "lib"), "-lamdhip64"])
     os.replace(tmp, LIB)
     return LIB

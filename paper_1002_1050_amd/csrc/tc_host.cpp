@@ -521,11 +521,26 @@ int adj_impl(int lmax, int mbmax, int nring, const double* cosbeta, int npair, c
         // one workgroup per column walks its ring tiles in order: tile 0 writes U and V, later tiles add
         rc = timed_launch(TC_OP_ADJ, stream, [&] { return tc::launch_adj(a, t, stream); });
         if (rc) return hip_fail(rc, "totalconv_adj launch");
+        // summed outputs: the pairs share this U, V, which one launch reads once for every
+        // pair's sky gradient; the beam gradients take one launch per pair
+        bool sky_shared = false;
+        if (p1 - p0 > 1 && alm_bar) {
+            tc::EpiPairsArgs e{};
+            e.lmax = lmax; e.mbmax = mbmax; e.P = L.P; e.sky_lmax = lmax; e.npair = p1 - p0;
+            e.U = a.U[0]; e.V = a.V[0];
+            for (int p = p0; p < p1; ++p) {
+                e.blm[p - p0] = blm[p];
+                e.alm_bar[p - p0] = alm_bar[p];
+                sky_shared |= alm_bar[p] != nullptr;
+            }
+            if (sky_shared && (rc = tc::launch_adj_sky_pairs(e, stream)))
+                return hip_fail(rc, "totalconv_adj epilogue launch");
+        }
         for (int p = p0; p < p1; ++p) {
             tc::EpiArgs e{};
             e.lmax = lmax; e.mbmax = mbmax; e.P = L.P; e.sky_lmax = lmax;
             e.U = a.U[0]; e.V = a.V[0]; e.alm = alm[p]; e.blm = blm[p];
-            e.alm_bar = alm_bar ? alm_bar[p] : nullptr;
+            e.alm_bar = (alm_bar && !sky_shared) ? alm_bar[p] : nullptr;
             e.blm_bar = blm_bar ? blm_bar[p] : nullptr;
             if ((rc = tc::launch_adj_epilogue(e, stream))) return hip_fail(rc, "totalconv_adj epilogue launch");
         }

@@ -90,6 +90,19 @@ struct EpiArgs {
     double* blm_bar;       // may be null
 };
 
+// The sky gradients of npair (2 or 3) (sky, beam) pairs that share one cotangent and so one U, V
+// (the polarised adjoint with summed outputs); every beam has the rows -mbmax .. mbmax.
+struct EpiPairsArgs {
+    int lmax, mbmax;
+    int sky_lmax;          // packing lmax of every alm_bar
+    int npair;
+    long long P;
+    const double* U;
+    const double* V;
+    const double* blm[3];
+    double* alm_bar[3];    // entries may be null (that pair's sky gradient is not stored)
+};
+
 // Full matrix d^l_{m m'} at one l: the m' recursion on the triangle 0 <= m <= m' <= l
 // at beta (side 0) and at pi - beta (side 1), written out with its symmetric images.
 struct MatrixArgs {
@@ -125,6 +138,8 @@ int launch_fwd(const FwdArgs& a, Tile t, void* stream);
 int launch_beam_symmetry(const double* blm, int lmax, int mbmax, int* sym, void* stream);
 int launch_adj(const AdjArgs& a, Tile t, void* stream);
 int launch_adj_epilogue(const EpiArgs& e, void* stream);
+// tc_epilogue.hip: the sky gradients of every pair in one launch, U and V read once.
+int launch_adj_sky_pairs(const EpiPairsArgs& e, void* stream);
 
 // Batched launches: one workgroup per item; forward items are (walk, column, ring tile) triples,
 // adjoint items (detector, column) pairs (the workgroup walks every ring tile of the column).

@@ -22,6 +22,7 @@ int launch_fwd(const FwdArgs&, Tile, void*) { return kNoKernel; }
 int launch_beam_symmetry(const double*, int, int, int*, void*) { return kNoKernel; }
 int launch_adj(const AdjArgs&, Tile, void*) { return kNoKernel; }
 int launch_adj_epilogue(const EpiArgs&, void*) { return kNoKernel; }
+int launch_adj_sky_pairs(const EpiPairsArgs&, void*) { return kNoKernel; }
 int launch_fwd_items(const FwdArgs*, const int*, int, Tile, void*) { return kNoKernel; }
 int fwd_walk_pairs(Tile t) { return t.R >= 8 ? 2 : 4; }
 int adj_walk_pairs_of(Tile t) { return (t.R <= 4 && t.TB <= 32) ? 2 : 1; }

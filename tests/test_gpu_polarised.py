@@ -119,6 +119,29 @@ def test_polarised_adjoint(B, orc, summed):
         assert torch.equal(gb2[p], gb[p])
 
 
+@pytest.mark.parametrize("npair", [2, 3])
+@pytest.mark.parametrize("L,M,n", [(150, 6, 1200), (300, 4, 701)])
+def test_polarised_summed_adjoint_equals_scalar_adjoints(B, L, M, n, npair):
+    """Summed outputs: the pairs share one cotangent and so one U, V, which one launch reads for
+    every pair's sky gradient.  Each pair's sky and beam gradients equal, bit for bit, those of a
+    scalar adjoint of that cotangent with the pair's sky and beam; requesting only the sky
+    gradients gives the same sky gradients."""
+    x = S.ring_cosines(n)
+    alms, blms = pairs(L, M, npair, 700)
+    da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+    G = dev(S.random_cbar(L, M, n, 800))
+    say(f"adj_pol summed vs scalar adjoints L={L} M={M} nring={n} npair={npair}")
+    ga, gb = B.totalconv_adj_pol_x(L, M, x, da, db, [G], B.TC_POL_SUM)
+    for p in range(npair):
+        sa, sb = B.totalconv_adj_x(L, M, x, da[p], db[p], G)
+        assert torch.equal(ga[p], sa), f"sky gradient of pair {p}"
+        assert torch.equal(gb[p], sb), f"beam gradient of pair {p}"
+    ga2, gb2 = B.totalconv_adj_pol_x(L, M, x, da, db, [G], B.TC_POL_SUM, want_blm=False)
+    assert all(g is None for g in gb2)
+    for p in range(npair):
+        assert torch.equal(ga2[p], ga[p])
+
+
 def test_polarised_rejects_bad_arguments(B):
     L, M = 20, 2
     x = S.ring_cosines(41)
