@@ -237,3 +237,26 @@ def test_polarised_full_size_sampled(B, orc):
     gt = column_gate(got_t, ref[0] + ref[1] + ref[2])
     say(f"  {mb.size} columns: separate {gs:.2e}, summed {gt:.2e}")
     assert gs <= GATE and gt <= GATE
+
+
+def test_polarised_summed_adjoint_full_size_equals_scalar_adjoints(B):
+    """The summed-output adjoint at the lmax 4096 workload (three pairs, built-in tile): every
+    pair's sky and beam gradients equal, bit for bit, those of a scalar adjoint of the same
+    cotangent (the sky gradients of all pairs come from one launch over the shared U, V)."""
+    w = S.WORKLOADS["lmax4096"]
+    L, M, x = w.lmax, w.mbmax, w.xring()
+    alms = [w.alm()] + [S.sky_alm(L, w.sky_seed + 1 + p) for p in range(2)]
+    blms = [w.blm()] + [S.random_beam(L, M, 77 + p) for p in range(2)]
+    da, db = [dev(a) for a in alms], [dev(b) for b in blms]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4096)
+    G = torch.randn((2 * M + 1, L + 1, x.size), dtype=torch.complex128, device="cuda", generator=g)
+    say(f"adj_pol summed full size L={L} M={M} nring={x.size}, three pairs, vs scalar adjoints")
+    ga, gb = B.totalconv_adj_pol_x(L, M, x, da, db, [G], B.TC_POL_SUM)
+    for p in range(3):
+        sa, sb = B.totalconv_adj_x(L, M, x, da[p], db[p], G)
+        assert torch.equal(ga[p], sa), f"sky gradient of pair {p}"
+        assert torch.equal(gb[p], sb), f"beam gradient of pair {p}"
+        del sa, sb
+    del G
+    torch.cuda.empty_cache()
