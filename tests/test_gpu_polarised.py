@@ -120,7 +120,7 @@ def test_polarised_adjoint(B, orc, summed):
 
 
 @pytest.mark.parametrize("npair", [2, 3])
-@pytest.mark.parametrize("L,M,n", [(150, 6, 1200), (300, 4, 701)])
+@pytest.mark.parametrize("L,M,n", [(150, 6, 1200), (300, 4, 701), (6, 6, 3), (0, 0, 1)])
 def test_polarised_summed_adjoint_equals_scalar_adjoints(B, L, M, n, npair):
     """Summed outputs: the pairs share one cotangent and so one U, V, which one launch reads for
     every pair's sky gradient.  Each pair's sky and beam gradients equal, bit for bit, those of a
